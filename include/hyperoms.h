@@ -1,0 +1,257 @@
+/*
+ * hyperoms.h — C ABI of libhyperoms, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of HyperOMS open modification spectral library
+ * search (Kang, Xu, Bittremieux, Rosing; arXiv 2211.16422):
+ *
+ *   spectrum vectors --(Eq. 1 encoding, Section 3.3)--> binary hypervectors
+ *   --(charge + precursor m/z filter and Hamming top-1, Section 3.4)--> best
+ *   library match per query.
+ *
+ * Conventions
+ *  - Every function returns homs_status (0 = success, < 0 = error) unless it
+ *    is documented otherwise; no C++ exception crosses this boundary. The
+ *    message of the last failure on a context is homs_last_error(ctx); errors
+ *    raised before a context exists are reported by homs_last_error(NULL)
+ *    (per thread).
+ *  - Pointers prefixed h_ are host memory, d_ are device memory on the
+ *    context's device. All buffers are owned by the caller and only used for
+ *    the duration of the call, except where stated; the context owns its
+ *    codebook, its sorted library and its workspaces.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it; calls documented as synchronous wait for
+ *    it before returning.
+ *  - Hypervectors are packed rows of D/32 uint32 words: bit d of a row is bit
+ *    (d % 32) of word d / 32. A 0 bit stands for the bipolar component +1 and
+ *    a 1 bit for -1, so the element-wise product of Eq. 1 is XOR.
+ *  - After HOMS_E_DEVICE the context is unusable and only homs_destroy is
+ *    valid. Other failures leave the context as it was.
+ */
+#ifndef HYPEROMS_H
+#define HYPEROMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t homs_status;
+
+#define HOMS_OK 0
+#define HOMS_E_INVALID (-1)     /* bad argument */
+#define HOMS_E_OOM (-2)         /* device or host allocation failed */
+#define HOMS_E_DEVICE (-3)      /* HIP runtime or kernel failure (sticky) */
+#define HOMS_E_STATE (-4)       /* call not valid in the context's state */
+#define HOMS_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+
+typedef struct homs_ctx homs_ctx;
+
+/*
+ * Method parameters (Table 1; Section 4.2).
+ *  dim          D, hypervector bits; a multiple of 512 in [512, 32768]
+ *               (Section 4.2 uses 8192).
+ *  n_levels     Q, intensity levels, 2..255 (Section 4.2 uses 16).
+ *  top_n        most intense peaks kept per spectrum (Table 1: 50), >= 1.
+ *  mz_min/max   fragment m/z range [mz_min, mz_max) (Table 1: 101 / 1500).
+ *  bins_per_da  1 / bin width (Table 1: 20 for 0.05 Da, 25 for 0.04 Da).
+ *  noise_frac   peaks below noise_frac x the most intense peak are dropped
+ *               (Section 3.2: 0.01).
+ *  id_flips     alpha, components flipped between the first and the last
+ *               position hypervector (Section 3.3.1); 0 means D/2.
+ *  charge_match 1: candidates must share the query's charge (Section 3.4);
+ *               0: charge is ignored.
+ *  seed         seed of the codebook's SplitMix64 stream.
+ */
+typedef struct homs_params {
+    uint32_t struct_size; /* sizeof(homs_params) */
+    uint32_t dim;
+    uint32_t n_levels;
+    uint32_t top_n;
+    double mz_min;
+    double mz_max;
+    double bins_per_da;
+    double noise_frac;
+    uint32_t id_flips;
+    uint32_t charge_match;
+    uint64_t seed;
+} homs_params;
+
+/* Precursor tolerance (Section 3.4; Table 1): kind 0 = +-value Da,
+ * kind 1 = +-value ppm of the query precursor m/z, i.e. pmz * value / 1e6.
+ * A library spectrum is a candidate when lo <= pmz_ref <= hi with
+ * lo = pmz - tol and hi = pmz + tol computed in float64. */
+#define HOMS_TOL_DA 0
+#define HOMS_TOL_PPM 1
+typedef struct homs_window {
+    int32_t kind;
+    int32_t reserved;
+    double value;
+} homs_window;
+
+/* Search engines for homs_search_window. POPCOUNT: XOR + population count
+ * on packed words (Section 3.4 with the bit packing of Section 4.1).
+ * MFMA_I8 / MFMA_F8: the same distances as H = (D - <x, y>) / 2 of the
+ * bipolar vectors, contracted on matrix cores with int8 (int32 accumulate)
+ * or fp8 e4m3 (fp32 accumulate) operands; exact for D <= 16384. */
+#define HOMS_ENGINE_POPCOUNT 0
+#define HOMS_ENGINE_MFMA_I8 1
+#define HOMS_ENGINE_MFMA_F8 2
+
+/* Fills *p with Table 1 / Section 4.2 defaults (D = 8192, Q = 16, top 50,
+ * [101, 1500) m/z, 0.05 Da bins, 1% noise floor, alpha = D/2, charge match,
+ * seed 0). */
+homs_status homs_params_default(homs_params *p);
+
+/* Number of m/z bins f = ceil((mz_max - mz_min) * bins_per_da), i.e. the
+ * number of position hypervectors; -1 if p is invalid. */
+int64_t homs_num_bins(const homs_params *p);
+
+const char *homs_status_string(homs_status s);
+const char *homs_last_error(const homs_ctx *ctx);
+
+/*
+ * Host preprocessing of raw spectra into spectrum vectors (Section 3.2;
+ * Table 1). Per spectrum: keep peaks with mz_min <= mz < mz_max; drop peaks
+ * below noise_frac x the most intense remaining peak; keep the top_n most
+ * intense (ties: lower m/z, then earlier peak); take the square root of each
+ * intensity; bin = floor((mz - mz_min) * bins_per_da) (clamped to f - 1);
+ * sum the values of peaks sharing a bin in ascending m/z order; divide by
+ * the largest bin value; level = min(Q - 1, floor(v * Q)).
+ * In:  n spectra; h_offsets[n + 1] (CSR, non-decreasing, h_offsets[0] = 0);
+ *      h_mz and h_intensity[h_offsets[n]] (finite; intensity >= 0).
+ * Out: h_out_offsets[n + 1]; h_out_bin (int32) and h_out_level (uint8), each
+ *      with room for h_offsets[n] entries, receive per spectrum its unique
+ *      bins in ascending order; *out_total = number of entries written.
+ * Synchronous, host only; uses up to n_threads host threads (0 = all).
+ */
+homs_status homs_preprocess(const homs_params *p, int64_t n, const int64_t *h_offsets,
+                            const double *h_mz, const double *h_intensity,
+                            int64_t *h_out_offsets, int32_t *h_out_bin,
+                            uint8_t *h_out_level, int64_t *out_total, int32_t n_threads);
+
+/*
+ * Creates a context on HIP device `device` and generates the position and
+ * level hypervectors from p->seed (Sections 3.3.1, 3.3.2): F_0 and the level
+ * base L_0 are random bits, F_i flips the first floor(alpha*i/(f-1))
+ * components of a random order of the D components, L_j flips the first
+ * floor((D/2)*j/(Q-1)) components of another random order. Random numbers
+ * come from one SplitMix64 stream (Steele et al., OOPSLA 2014) started at
+ * the seed and consumed as: F_0 bits (D/64 outputs, bit d = bit d%64 of
+ * output d/64), Fisher-Yates order of F (i = D-1..1, j = output mod (i+1)),
+ * L_0 bits, order of L. Synchronous.
+ */
+homs_status homs_create(const homs_params *p, int32_t device, homs_ctx **out);
+
+/* The same tables as homs_create generates, computed on the host into
+ * h_id (f x D/32 words) and h_level (Q x D/32 words); no device needed. */
+homs_status homs_generate_codebook(const homs_params *p, uint32_t *h_id, uint32_t *h_level);
+void homs_destroy(homs_ctx *ctx);
+
+/* Replaces the position table (f rows of D/32 words) and/or the level table
+ * (Q rows) with caller-supplied host tables; NULL keeps the current one.
+ * Invalidates an encoded library (state error on the next search until the
+ * library is encoded again). Synchronous. */
+homs_status homs_set_codebook(homs_ctx *ctx, const uint32_t *h_id, const uint32_t *h_level);
+/* Copies the current tables to host buffers of f x D/32 and Q x D/32 words
+ * (either may be NULL). Synchronous. */
+homs_status homs_get_codebook(homs_ctx *ctx, uint32_t *h_id, uint32_t *h_level);
+
+/*
+ * Encodes n spectrum vectors with Eq. 1 (Section 3.3): I = sum over peaks
+ * (bin i, level j) of F_i (*) L_j, then bit d = 0 if I_d > 0 and 1 otherwise
+ * (so a tie, and every bit of a spectrum without peaks, is 1).
+ * In:  d_offsets[n + 1] (int64 CSR); d_bin[...] (int32, each < f, unique
+ *      within a spectrum), d_level[...] (uint8, each < Q).
+ * Out: d_out[n][D/32] packed rows (uint32, 16-byte aligned) in input order.
+ * Asynchronous on `stream`. A peak with an out-of-range bin or level is
+ * skipped and raises a device error flag read by homs_device_errors().
+ */
+homs_status homs_encode_queries(homs_ctx *ctx, int64_t n, const int64_t *d_offsets,
+                                const int32_t *d_bin, const uint8_t *d_level, uint32_t *d_out,
+                                void *stream);
+
+/*
+ * Encodes the reference library (Section 3.3; references are encoded once
+ * and reused) and keeps it on the device sorted by (charge, precursor m/z,
+ * library index), which makes every query's candidates (Section 3.4) one
+ * contiguous range. Library index = position in the input (references and
+ * decoys as the caller orders them); 0 <= n < 2^31.
+ * In: CSR as for homs_encode_queries; d_pmz[n] float64; d_charge[n] int8.
+ * Replaces any previous library. Synchronous (waits for `stream`); returns
+ * HOMS_E_INVALID if a bin or level was out of range.
+ */
+homs_status homs_encode_library(homs_ctx *ctx, int64_t n, const int64_t *d_offsets,
+                                const int32_t *d_bin, const uint8_t *d_level,
+                                const double *d_pmz, const int8_t *d_charge, void *stream);
+
+/* Number of library spectra (0 before homs_encode_library). */
+homs_status homs_library_size(const homs_ctx *ctx, int64_t *n);
+
+/* Copies the encoded library into d_out[n][D/32] in library-index order.
+ * Asynchronous on `stream`. */
+homs_status homs_library_export(homs_ctx *ctx, uint32_t *d_out, void *stream);
+
+/*
+ * Candidate ranges (Section 3.4): for each query, [d_lo[q], d_hi[q]) in the
+ * context's sorted library order; the count of candidates is hi - lo. NaN
+ * precursors give empty ranges. Asynchronous on `stream`.
+ */
+homs_status homs_window_bounds(homs_ctx *ctx, int64_t nq, const double *d_q_pmz,
+                               const int8_t *d_q_charge, const homs_window *win,
+                               int64_t *d_lo, int64_t *d_hi, void *stream);
+
+/*
+ * Open (or standard) search, Section 3.4: for every query, the candidate
+ * with the smallest Hamming distance (largest Hamming similarity
+ * D - distance), equal distances going to the lowest library index.
+ * In:  d_q_hv[nq][D/32] (16-byte aligned), d_q_pmz[nq], d_q_charge[nq],
+ *      one window for all queries, engine = HOMS_ENGINE_*.
+ * Out: d_out_idx[nq] (int64 library index, -1 if no candidate),
+ *      d_out_dist[nq] (int32 Hamming distance, -1 if no candidate).
+ * Asynchronous on `stream`; the context's workspace grows on first use of a
+ * larger nq (a device allocation), so concurrent calls on one context race.
+ */
+homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                               const double *d_q_pmz, const int8_t *d_q_charge,
+                               const homs_window *win, int32_t engine, int64_t *d_out_idx,
+                               int32_t *d_out_dist, void *stream);
+
+/*
+ * Every candidate of every query with its Hamming distance (test support).
+ * d_row_off[nq + 1] are prefix sums of hi - lo from homs_window_bounds; query
+ * q's candidates are written to [d_row_off[q], d_row_off[q + 1]) of d_out_idx
+ * (library index) and d_out_dist, in sorted-library order. Asynchronous.
+ */
+homs_status homs_debug_distances(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                                 const double *d_q_pmz, const int8_t *d_q_charge,
+                                 const homs_window *win, const int64_t *d_row_off,
+                                 int64_t *d_out_idx, int32_t *d_out_dist, void *stream);
+
+/* Reads and clears the context's device error flags (bit 0: a bin or level
+ * out of range in an encode). Synchronous (waits for `stream`). */
+homs_status homs_device_errors(homs_ctx *ctx, uint32_t *flags, void *stream);
+
+/*
+ * Kernel timing (measurement support). While enabled, every search and
+ * query-encode call records HIP events on its stream around its main kernel;
+ * homs_profile_read waits for those events, returns the accumulated times
+ * and launch counts since the last read, and resets them.
+ *  search_ms/search_launches: the Hamming search kernel (any engine);
+ *  encode_ms/encode_launches: the encode kernel of homs_encode_queries;
+ *  prep_ms: window, ordering and result kernels around the search kernel.
+ */
+typedef struct homs_profile {
+    double search_ms;
+    double encode_ms;
+    double prep_ms;
+    int64_t search_launches;
+    int64_t encode_launches;
+} homs_profile;
+homs_status homs_profile_enable(homs_ctx *ctx, int32_t enable);
+homs_status homs_profile_read(homs_ctx *ctx, homs_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPEROMS_H */

@@ -1,0 +1,645 @@
+// C ABI of libhyperoms: argument validation, context and memory management,
+// and the order of kernel launches for each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "codebook.h"
+#include "internal.h"
+#include "preprocess.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+homs_status fail(homs_ctx* c, homs_status s, const std::string& msg)
+{
+    if (c) {
+        c->err = msg;
+        if (s == HOMS_E_DEVICE) c->dead = true;
+    } else {
+        g_last_error = msg;
+    }
+    return s;
+}
+
+homs_status hip_fail(homs_ctx* c, hipError_t e, const char* what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        return fail(c, HOMS_E_OOM, msg);
+    }
+    return fail(c, HOMS_E_DEVICE, msg);
+}
+
+#define HIP_TRY(c, expr, what)                      \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return hip_fail((c), e_, (what)); \
+    } while (0)
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool params_valid(const homs_params* p, std::string* why)
+{
+    if (!p) {
+        *why = "params is NULL";
+        return false;
+    }
+    if (p->struct_size != sizeof(homs_params)) {
+        *why = "params.struct_size != sizeof(homs_params)";
+        return false;
+    }
+    if (p->dim < 512 || p->dim > 32768 || p->dim % 512 != 0) {
+        *why = "dim must be a multiple of 512 in [512, 32768]";
+        return false;
+    }
+    if (p->n_levels < 2 || p->n_levels > 255) {
+        *why = "n_levels must be in [2, 255]";
+        return false;
+    }
+    if (p->top_n < 1) {
+        *why = "top_n must be >= 1";
+        return false;
+    }
+    if (!std::isfinite(p->mz_min) || !std::isfinite(p->mz_max) || !(p->mz_max > p->mz_min) ||
+        !std::isfinite(p->bins_per_da) || !(p->bins_per_da > 0.0) ||
+        !std::isfinite(p->noise_frac) || p->noise_frac < 0.0 || p->noise_frac > 1.0) {
+        *why = "invalid m/z range, bin width or noise fraction";
+        return false;
+    }
+    const double f = std::ceil((p->mz_max - p->mz_min) * p->bins_per_da);
+    if (!(f >= 1.0) || f > 16777216.0) {
+        *why = "number of m/z bins must be in [1, 2^24]";
+        return false;
+    }
+    if (p->id_flips > p->dim) {
+        *why = "id_flips must be <= dim";
+        return false;
+    }
+    if (p->charge_match > 1) {
+        *why = "charge_match must be 0 or 1";
+        return false;
+    }
+    return true;
+}
+
+bool window_valid(const homs_window* w, std::string* why)
+{
+    if (!w) {
+        *why = "window is NULL";
+        return false;
+    }
+    if (w->kind != HOMS_TOL_DA && w->kind != HOMS_TOL_PPM) {
+        *why = "window kind must be HOMS_TOL_DA or HOMS_TOL_PPM";
+        return false;
+    }
+    if (!std::isfinite(w->value) || w->value < 0.0) {
+        *why = "window value must be finite and >= 0";
+        return false;
+    }
+    return true;
+}
+
+homs_status usable(homs_ctx* c)
+{
+    if (!c) return fail(nullptr, HOMS_E_INVALID, "ctx is NULL");
+    if (c->dead) return fail(c, HOMS_E_DEVICE, "context is in a device-error state: " + c->err);
+    return HOMS_OK;
+}
+
+void free_library(homs::Library& L)
+{
+    if (L.hv) (void)hipFree(L.hv);
+    if (L.pmz) (void)hipFree(L.pmz);
+    if (L.charge) (void)hipFree(L.charge);
+    if (L.orig) (void)hipFree(L.orig);
+    L = homs::Library{};
+}
+
+// Grows the context's workspace to at least `bytes` (synchronising first).
+homs_status ensure_workspace(homs_ctx* c, size_t bytes, hipStream_t s)
+{
+    if (c->ws.bytes >= bytes) return HOMS_OK;
+    HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (c->ws.ptr) (void)hipFree(c->ws.ptr);
+    c->ws = homs::Workspace{};
+    const size_t want = bytes + bytes / 4;
+    HIP_TRY(c, hipMalloc(&c->ws.ptr, want), "hipMalloc(workspace)");
+    c->ws.bytes = want;
+    return HOMS_OK;
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Per-call search scratch carved out of the workspace.
+struct SearchScratch {
+    int64_t* lo;
+    int64_t* hi;
+    uint64_t* keys;
+    uint64_t* qk_a;
+    uint64_t* qk_b;
+    uint32_t* qp_a;
+    uint32_t* qp_b;
+    int64_t* tile_lo;
+    int64_t* tile_hi;
+    void* sort_tmp;
+    size_t sort_bytes;
+};
+
+size_t search_scratch_bytes(int64_t nq, int tile)
+{
+    const int64_t nt = (nq + tile - 1) / tile;
+    return 2 * al(nq * 8) + al(nq * 8) + 2 * al(nq * 8) + 2 * al(nq * 4) + 2 * al(nt * 8) +
+           homs::query_sort_temp_bytes(nq);
+}
+
+SearchScratch carve(void* base, int64_t nq, int tile)
+{
+    const int64_t nt = (nq + tile - 1) / tile;
+    char* p = (char*)base;
+    SearchScratch s{};
+    s.lo = (int64_t*)p;
+    p += al(nq * 8);
+    s.hi = (int64_t*)p;
+    p += al(nq * 8);
+    s.keys = (uint64_t*)p;
+    p += al(nq * 8);
+    s.qk_a = (uint64_t*)p;
+    p += al(nq * 8);
+    s.qk_b = (uint64_t*)p;
+    p += al(nq * 8);
+    s.qp_a = (uint32_t*)p;
+    p += al(nq * 4);
+    s.qp_b = (uint32_t*)p;
+    p += al(nq * 4);
+    s.tile_lo = (int64_t*)p;
+    p += al(nt * 8);
+    s.tile_hi = (int64_t*)p;
+    p += al(nt * 8);
+    s.sort_tmp = p;
+    s.sort_bytes = homs::query_sort_temp_bytes(nq);
+    return s;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Records an event on `s` for profiling (nullptr when profiling is off).
+hipEvent_t prof_mark(homs_ctx* c, hipStream_t s)
+{
+    if (!c->prof.on) return nullptr;
+    hipEvent_t e = nullptr;
+    if (!c->prof.pool.empty()) {
+        e = c->prof.pool.back();
+        c->prof.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, s) != hipSuccess) {
+        c->prof.pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void prof_span(homs_ctx* c, hipEvent_t a, hipEvent_t b, int kind)
+{
+    if (a && b) c->prof.pending.push_back({a, b, kind});
+}
+
+}  // namespace
+
+extern "C" {
+
+homs_status homs_params_default(homs_params* p)
+{
+    if (!p) return fail(nullptr, HOMS_E_INVALID, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(homs_params);
+    p->dim = 8192;
+    p->n_levels = 16;
+    p->top_n = 50;
+    p->mz_min = 101.0;
+    p->mz_max = 1500.0;
+    p->bins_per_da = 20.0;
+    p->noise_frac = 0.01;
+    p->id_flips = 0;
+    p->charge_match = 1;
+    p->seed = 0;
+    return HOMS_OK;
+}
+
+int64_t homs_num_bins(const homs_params* p)
+{
+    std::string why;
+    if (!params_valid(p, &why)) return -1;
+    return (int64_t)std::ceil((p->mz_max - p->mz_min) * p->bins_per_da);
+}
+
+const char* homs_status_string(homs_status s)
+{
+    switch (s) {
+    case HOMS_OK: return "ok";
+    case HOMS_E_INVALID: return "invalid argument";
+    case HOMS_E_OOM: return "out of memory";
+    case HOMS_E_DEVICE: return "device error";
+    case HOMS_E_STATE: return "invalid state";
+    case HOMS_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* homs_last_error(const homs_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+homs_status homs_preprocess(const homs_params* p, int64_t n, const int64_t* h_offsets,
+                            const double* h_mz, const double* h_intensity, int64_t* h_out_offsets,
+                            int32_t* h_out_bin, uint8_t* h_out_level, int64_t* out_total,
+                            int32_t n_threads)
+{
+    std::string why;
+    if (!params_valid(p, &why)) return fail(nullptr, HOMS_E_INVALID, why);
+    if (n < 0 || !h_offsets || !h_out_offsets || !out_total)
+        return fail(nullptr, HOMS_E_INVALID, "n < 0 or NULL offsets/out_total");
+    if (n > 0 && h_offsets[n] > 0 && (!h_mz || !h_intensity || !h_out_bin || !h_out_level))
+        return fail(nullptr, HOMS_E_INVALID, "NULL peak arrays");
+    homs::PreprocessParams pp{p->mz_min,      p->mz_max, p->bins_per_da, p->noise_frac,
+                              p->top_n,       p->n_levels, homs_num_bins(p)};
+    try {
+        if (!homs::preprocess_spectra(pp, n, h_offsets, h_mz, h_intensity, h_out_offsets,
+                                      h_out_bin, h_out_level, out_total, n_threads, &why))
+            return fail(nullptr, HOMS_E_INVALID, why);
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, HOMS_E_OOM, "host allocation failed in preprocess");
+    } catch (const std::exception& e) {
+        return fail(nullptr, HOMS_E_INVALID, e.what());
+    }
+    return HOMS_OK;
+}
+
+homs_status homs_create(const homs_params* p, int32_t device, homs_ctx** out)
+{
+    std::string why;
+    if (!out) return fail(nullptr, HOMS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!params_valid(p, &why)) return fail(nullptr, HOMS_E_INVALID, why);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return fail(nullptr, HOMS_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(nullptr, HOMS_E_INVALID, "device out of range");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(nullptr, HOMS_E_DEVICE, "hipSetDevice failed");
+
+    homs_ctx* c = new (std::nothrow) homs_ctx();
+    if (!c) return fail(nullptr, HOMS_E_OOM, "host allocation failed");
+    c->p = *p;
+    if (c->p.id_flips == 0) c->p.id_flips = c->p.dim / 2;
+    c->device = device;
+    c->n_bins = homs_num_bins(p);
+    c->words = p->dim / 32;
+
+    std::vector<uint32_t> id, lv;
+    try {
+        id.resize((size_t)c->n_bins * c->words);
+        lv.resize((size_t)p->n_levels * c->words);
+    } catch (const std::bad_alloc&) {
+        delete c;
+        return fail(nullptr, HOMS_E_OOM, "host allocation failed (codebook)");
+    }
+    homs::generate_codebook(p->dim, (uint32_t)c->n_bins, p->n_levels, c->p.id_flips, p->seed,
+                            id.data(), lv.data());
+    hipError_t e = hipMalloc(&c->d_id, id.size() * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_level, lv.size() * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_err, 256);
+    if (e == hipSuccess) e = hipMemcpy(c->d_id, id.data(), id.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_level, lv.data(), lv.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->d_err, 0, 256);
+    if (e != hipSuccess) {
+        std::string msg = std::string("context setup: ") + hipGetErrorString(e);
+        homs_destroy(c);
+        return fail(nullptr, e == hipErrorOutOfMemory ? HOMS_E_OOM : HOMS_E_DEVICE, msg);
+    }
+    *out = c;
+    return HOMS_OK;
+}
+
+homs_status homs_generate_codebook(const homs_params* p, uint32_t* h_id, uint32_t* h_level)
+{
+    std::string why;
+    if (!params_valid(p, &why)) return fail(nullptr, HOMS_E_INVALID, why);
+    if (!h_id || !h_level) return fail(nullptr, HOMS_E_INVALID, "NULL output table");
+    const uint32_t alpha = p->id_flips == 0 ? p->dim / 2 : p->id_flips;
+    homs::generate_codebook(p->dim, (uint32_t)homs_num_bins(p), p->n_levels, alpha, p->seed, h_id,
+                            h_level);
+    return HOMS_OK;
+}
+
+void homs_destroy(homs_ctx* c)
+{
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    free_library(c->lib);
+    if (c->d_id) (void)hipFree(c->d_id);
+    if (c->d_level) (void)hipFree(c->d_level);
+    if (c->d_err) (void)hipFree(c->d_err);
+    if (c->ws.ptr) (void)hipFree(c->ws.ptr);
+    for (auto& sp : c->prof.pending) {
+        c->prof.pool.push_back(sp.a);
+        c->prof.pool.push_back(sp.b);
+    }
+    std::sort(c->prof.pool.begin(), c->prof.pool.end());
+    c->prof.pool.erase(std::unique(c->prof.pool.begin(), c->prof.pool.end()), c->prof.pool.end());
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+homs_status homs_set_codebook(homs_ctx* c, const uint32_t* h_id, const uint32_t* h_level)
+{
+    if (homs_status s = usable(c)) return s;
+    DeviceGuard g(c->device);
+    if (h_id)
+        HIP_TRY(c, hipMemcpy(c->d_id, h_id, (size_t)c->n_bins * c->words * 4, hipMemcpyHostToDevice),
+                "hipMemcpy(id table)");
+    if (h_level)
+        HIP_TRY(c, hipMemcpy(c->d_level, h_level, (size_t)c->p.n_levels * c->words * 4,
+                             hipMemcpyHostToDevice),
+                "hipMemcpy(level table)");
+    if (h_id || h_level) c->lib_valid = false;
+    return HOMS_OK;
+}
+
+homs_status homs_get_codebook(homs_ctx* c, uint32_t* h_id, uint32_t* h_level)
+{
+    if (homs_status s = usable(c)) return s;
+    DeviceGuard g(c->device);
+    if (h_id)
+        HIP_TRY(c, hipMemcpy(h_id, c->d_id, (size_t)c->n_bins * c->words * 4, hipMemcpyDeviceToHost),
+                "hipMemcpy(id table)");
+    if (h_level)
+        HIP_TRY(c, hipMemcpy(h_level, c->d_level, (size_t)c->p.n_levels * c->words * 4,
+                             hipMemcpyDeviceToHost),
+                "hipMemcpy(level table)");
+    return HOMS_OK;
+}
+
+homs_status homs_encode_queries(homs_ctx* c, int64_t n, const int64_t* d_offsets,
+                                const int32_t* d_bin, const uint8_t* d_level, uint32_t* d_out,
+                                void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "n must be in [0, 2^31)");
+    if (n == 0) return HOMS_OK;
+    if (!d_offsets || !d_bin || !d_level || !d_out)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_out)) return fail(c, HOMS_E_INVALID, "d_out must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    hipEvent_t e0 = prof_mark(c, (hipStream_t)stream);
+    HIP_TRY(c, homs::launch_encode(c, n, d_offsets, d_bin, d_level, nullptr, d_out,
+                                   (hipStream_t)stream),
+            "encode kernel");
+    prof_span(c, e0, prof_mark(c, (hipStream_t)stream), homs::kProfEncode);
+    return HOMS_OK;
+}
+
+homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets,
+                                const int32_t* d_bin, const uint8_t* d_level, const double* d_pmz,
+                                const int8_t* d_charge, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "n must be in [0, 2^31)");
+    if (n > 0 && (!d_offsets || !d_bin || !d_level || !d_pmz || !d_charge))
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    free_library(c->lib);
+    c->lib_valid = false;
+    if (n == 0) {
+        c->lib_valid = true;
+        return HOMS_OK;
+    }
+    homs::Library L;
+    L.n = n;
+    const size_t tmp_bytes = homs::library_sort_temp_bytes(n);
+    void* tmp = nullptr;
+    uint32_t* slot = nullptr;
+    hipError_t e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
+    if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
+    if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&L.orig, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc(&slot, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
+    if (e == hipSuccess)
+        e = homs::launch_library_sort(n, d_pmz, d_charge, c->p.charge_match != 0, tmp, tmp_bytes,
+                                      L.orig, L.pmz, L.charge, slot, s);
+    if (e == hipSuccess) e = homs::launch_encode(c, n, d_offsets, d_bin, d_level, slot, L.hv, s);
+    uint32_t flags = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, c->d_err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (slot) (void)hipFree(slot);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        free_library(L);
+        return hip_fail(c, e, "encode_library");
+    }
+    if (flags & homs::kErrRange) {
+        free_library(L);
+        (void)hipMemset(c->d_err, 0, 4);
+        return fail(c, HOMS_E_INVALID, "a bin or level is out of range");
+    }
+    c->lib = L;
+    c->lib_valid = true;
+    return HOMS_OK;
+}
+
+homs_status homs_library_size(const homs_ctx* c, int64_t* n)
+{
+    if (!c || !n) return fail(nullptr, HOMS_E_INVALID, "NULL argument");
+    *n = c->lib_valid ? c->lib.n : 0;
+    return HOMS_OK;
+}
+
+homs_status homs_library_export(homs_ctx* c, uint32_t* d_out, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (c->lib.n == 0) return HOMS_OK;
+    if (!d_out || !aligned16(d_out)) return fail(c, HOMS_E_INVALID, "d_out NULL or misaligned");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, homs::launch_gather_rows(c->lib.n, c->words, c->lib.hv, c->lib.orig, d_out,
+                                        (hipStream_t)stream),
+            "export kernel");
+    return HOMS_OK;
+}
+
+homs_status homs_window_bounds(homs_ctx* c, int64_t nq, const double* d_q_pmz,
+                               const int8_t* d_q_charge, const homs_window* win, int64_t* d_lo,
+                               int64_t* d_hi, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_pmz || !d_q_charge || !d_lo || !d_hi) return fail(c, HOMS_E_INVALID, "NULL pointer");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, homs::launch_window_bounds(c, nq, d_q_pmz, d_q_charge, win->kind, win->value,
+                                          nullptr, nullptr, d_lo, d_hi, (hipStream_t)stream),
+            "window kernel");
+    return HOMS_OK;
+}
+
+homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                               const double* d_q_pmz, const int8_t* d_q_charge,
+                               const homs_window* win, int32_t engine, int64_t* d_out_idx,
+                               int32_t* d_out_dist, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (engine != HOMS_ENGINE_POPCOUNT && engine != HOMS_ENGINE_MFMA_I8 &&
+        engine != HOMS_ENGINE_MFMA_F8)
+        return fail(c, HOMS_E_INVALID, "unknown engine");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    if (engine != HOMS_ENGINE_POPCOUNT)
+        return fail(c, HOMS_E_UNSUPPORTED, "MFMA engines are not built yet");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int tile = homs::search_popcount_tile();
+    if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, tile), s)) return st;
+    SearchScratch w = carve(c->ws.ptr, nq, tile);
+
+    hipEvent_t e0 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_window_bounds(c, nq, d_q_pmz, d_q_charge, win->kind, win->value,
+                                          nullptr, nullptr, w.lo, w.hi, s),
+            "window kernel");
+    uint32_t* qperm = nullptr;
+    HIP_TRY(c, homs::launch_query_sort(nq, d_q_pmz, d_q_charge, c->p.charge_match != 0, w.sort_tmp,
+                                       w.sort_bytes, w.qk_a, w.qk_b, w.qp_a, w.qp_b, &qperm, s),
+            "query sort");
+    HIP_TRY(c, homs::launch_tile_bounds(nq, qperm, w.lo, w.hi, tile, w.tile_lo, w.tile_hi, s),
+            "tile bounds kernel");
+    HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
+    homs::TilePlan plan;
+    hipEvent_t e1 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, w.lo, w.hi, w.tile_lo, w.tile_hi,
+                                            plan, w.keys, s),
+            "search kernel");
+    hipEvent_t e2 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");
+    hipEvent_t e3 = prof_mark(c, s);
+    prof_span(c, e0, e1, homs::kProfPrep);
+    prof_span(c, e1, e2, homs::kProfSearch);
+    prof_span(c, e2, e3, homs::kProfPrep);
+    return HOMS_OK;
+}
+
+homs_status homs_debug_distances(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                                 const double* d_q_pmz, const int8_t* d_q_charge,
+                                 const homs_window* win, const int64_t* d_row_off,
+                                 int64_t* d_out_idx, int32_t* d_out_dist, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_row_off || !d_out_idx || !d_out_dist)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int tile = homs::search_popcount_tile();
+    if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, tile), s)) return st;
+    SearchScratch w = carve(c->ws.ptr, nq, tile);
+    HIP_TRY(c, homs::launch_window_bounds(c, nq, d_q_pmz, d_q_charge, win->kind, win->value,
+                                          nullptr, nullptr, w.lo, w.hi, s),
+            "window kernel");
+    HIP_TRY(c, homs::launch_debug_distances(c, nq, d_q_hv, w.lo, w.hi, d_row_off, d_out_idx,
+                                            d_out_dist, s),
+            "debug distances kernel");
+    return HOMS_OK;
+}
+
+homs_status homs_device_errors(homs_ctx* c, uint32_t* flags, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!flags) return fail(c, HOMS_E_INVALID, "flags is NULL");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t f = 0;
+    HIP_TRY(c, hipMemcpyAsync(&f, c->d_err, 4, hipMemcpyDeviceToHost, s), "read error flags");
+    HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    HIP_TRY(c, hipMemsetAsync(c->d_err, 0, 4, s), "clear error flags");
+    HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    *flags = f;
+    return HOMS_OK;
+}
+
+homs_status homs_profile_enable(homs_ctx* c, int32_t enable)
+{
+    if (homs_status s = usable(c)) return s;
+    c->prof.on = enable != 0;
+    return HOMS_OK;
+}
+
+homs_status homs_profile_read(homs_ctx* c, homs_profile* out)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!out) return fail(c, HOMS_E_INVALID, "out is NULL");
+    DeviceGuard g(c->device);
+    for (auto& sp : c->prof.pending) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventSynchronize(sp.b), "hipEventSynchronize");
+        HIP_TRY(c, hipEventElapsedTime(&ms, sp.a, sp.b), "hipEventElapsedTime");
+        c->prof.ms[sp.kind] += ms;
+        c->prof.launches[sp.kind] += 1;
+    }
+    // spans share their boundary events; return each event to the pool once
+    std::vector<hipEvent_t> seen;
+    for (auto& sp : c->prof.pending)
+        for (hipEvent_t e : {sp.a, sp.b})
+            if (std::find(seen.begin(), seen.end(), e) == seen.end()) seen.push_back(e);
+    for (hipEvent_t e : seen) c->prof.pool.push_back(e);
+    c->prof.pending.clear();
+    out->search_ms = c->prof.ms[homs::kProfSearch];
+    out->encode_ms = c->prof.ms[homs::kProfEncode];
+    out->prep_ms = c->prof.ms[homs::kProfPrep];
+    out->search_launches = c->prof.launches[homs::kProfSearch];
+    out->encode_launches = c->prof.launches[homs::kProfEncode];
+    for (int k = 0; k < 3; ++k) {
+        c->prof.ms[k] = 0;
+        c->prof.launches[k] = 0;
+    }
+    return HOMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Eq. 1 encoding (Section 3.3) on gfx950.
+//
+// One group of D/128 consecutive lanes encodes one spectrum; lane w owns the
+// 128 components 128w .. 128w+127 (one uint4 of the packed row). For every
+// peak (bin i, level j) the lane loads its uint4 of F_i (a coalesced 16-byte
+// load: the group reads the whole 1 KiB row at D = 8192) and of L_j, binds
+// them with XOR (bit 0 = +1, so the bipolar product is XOR) and adds the
+// 128 resulting bits into bit-sliced counters: plane k holds bit k of the
+// number of -1 components seen so far, updated with a ripple of half adders.
+// The bipolar sum is I = n - 2c (n peaks, c components equal to -1), so the
+// binarised bit (1 unless I > 0) is c >= ceil(n/2), evaluated on the planes
+// with a bit-sliced comparison against that constant.
+#include "internal.h"
+
+namespace homs {
+namespace {
+
+struct U4 {
+    uint32_t v[4];
+};
+
+template <int P>
+__device__ __forceinline__ void add_bits(U4 (&c)[P], U4 x)
+{
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t carry = c[k].v[e] & x.v[e];
+            c[k].v[e] ^= x.v[e];
+            x.v[e] = carry;
+        }
+    }
+}
+
+// bit-sliced (count >= t) for a constant t < 2^P
+template <int P>
+__device__ __forceinline__ U4 at_least(const U4 (&c)[P], uint32_t t)
+{
+    U4 gt, eq;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        gt.v[e] = 0u;
+        eq.v[e] = ~0u;
+    }
+#pragma unroll
+    for (int k = P - 1; k >= 0; --k) {
+        const bool tk = (t >> k) & 1u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (tk) {
+                eq.v[e] &= c[k].v[e];
+            } else {
+                gt.v[e] |= eq.v[e] & c[k].v[e];
+                eq.v[e] &= ~c[k].v[e];
+            }
+        }
+    }
+    U4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r.v[e] = gt.v[e] | eq.v[e];
+    return r;
+}
+
+template <int P>
+__device__ __forceinline__ U4 encode_one(const uint4* __restrict__ id, const uint4* __restrict__ lv,
+                                         uint32_t w4, uint32_t lane, int64_t a, int64_t b,
+                                         const int32_t* __restrict__ bin,
+                                         const uint8_t* __restrict__ level, int64_t n_bins,
+                                         uint32_t n_levels, uint32_t* __restrict__ err)
+{
+    U4 c[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[k].v[e] = 0u;
+    uint32_t n_ok = 0;
+    for (int64_t p = a; p < b; ++p) {
+        const int32_t bi = bin[p];
+        const uint32_t lj = level[p];
+        if (bi < 0 || (int64_t)bi >= n_bins || lj >= n_levels) {
+            if (lane == 0) atomicOr(err, kErrRange);
+            continue;
+        }
+        const uint4 f = id[(size_t)bi * w4 + lane];
+        const uint4 l = lv[(size_t)lj * w4 + lane];
+        U4 x;
+        x.v[0] = f.x ^ l.x;
+        x.v[1] = f.y ^ l.y;
+        x.v[2] = f.z ^ l.z;
+        x.v[3] = f.w ^ l.w;
+        add_bits<P>(c, x);
+        ++n_ok;
+    }
+    return at_least<P>(c, (n_ok + 1u) / 2u);
+}
+
+__global__ __launch_bounds__(256) void encode_kernel(
+    const uint4* __restrict__ id, const uint4* __restrict__ lv, uint32_t w4, uint32_t per_block,
+    int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ bin,
+    const uint8_t* __restrict__ level, int64_t n_bins, uint32_t n_levels,
+    const uint32_t* __restrict__ slot, uint4* __restrict__ out, uint32_t* __restrict__ err)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t sub = t / w4;
+    const uint32_t lane = t - sub * w4;
+    if (sub >= per_block) return;
+    const int64_t s = (int64_t)blockIdx.x * per_block + sub;
+    if (s >= n) return;
+    const int64_t a = off[s], b = off[s + 1];
+    const int64_t np = b - a;
+    U4 r;
+    if (np < 64)
+        r = encode_one<6>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    else if (np < 256)
+        r = encode_one<8>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    else if (np < 65536)
+        r = encode_one<16>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    else
+        r = encode_one<32>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    const int64_t row = slot ? (int64_t)slot[s] : s;
+    out[(size_t)row * w4 + lane] = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+}
+
+}  // namespace
+
+hipError_t launch_encode(const homs_ctx* c, int64_t n, const int64_t* off, const int32_t* bin,
+                         const uint8_t* level, const uint32_t* slot, uint32_t* out,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const uint32_t w4 = c->words / 4;  // lanes per spectrum
+    const uint32_t per_block = 256u / w4;
+    const int64_t blocks = (n + per_block - 1) / per_block;
+    encode_kernel<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
+        reinterpret_cast<const uint4*>(c->d_id), reinterpret_cast<const uint4*>(c->d_level), w4,
+        per_block, n, off, bin, level, c->n_bins, c->p.n_levels, slot,
+        reinterpret_cast<uint4*>(out), c->d_err);
+    return hipGetLastError();
+}
+
+}  // namespace homs

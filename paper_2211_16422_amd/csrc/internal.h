@@ -1,0 +1,112 @@
+// Internal declarations shared by the host side of libhyperoms and its kernel
+// launchers. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "hyperoms.h"
+
+namespace homs {
+
+// Device-side error flag bits.
+constexpr uint32_t kErrRange = 1u;  // bin >= f or level >= Q in an encode
+
+struct Library {
+    int64_t n = 0;
+    uint32_t* hv = nullptr;      // [n][W] rows in sorted order
+    double* pmz = nullptr;       // [n] sorted precursor m/z
+    int8_t* charge = nullptr;    // [n] sorted charge (all 0 when charge is ignored)
+    uint32_t* orig = nullptr;    // [n] library index of each sorted row
+};
+
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Event-based kernel timing (homs_profile_*).
+enum ProfKind { kProfSearch = 0, kProfEncode = 1, kProfPrep = 2 };
+struct Profiler {
+    bool on = false;
+    struct Span {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Span> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+};
+
+}  // namespace homs
+
+struct homs_ctx {
+    homs_params p{};
+    int device = 0;
+    int64_t n_bins = 0;  // f
+    uint32_t words = 0;  // W = D / 32
+    uint32_t* d_id = nullptr;     // [f][W]
+    uint32_t* d_level = nullptr;  // [Q][W]
+    uint32_t* d_err = nullptr;    // device error flags
+    homs::Library lib;
+    bool lib_valid = false;
+    homs::Workspace ws;
+    homs::Profiler prof;
+    bool dead = false;
+    std::string err;
+};
+
+namespace homs {
+
+// ---- kernel launchers (each in its own translation unit) -------------------
+
+// encode.hip
+hipError_t launch_encode(const homs_ctx* c, int64_t n, const int64_t* off, const int32_t* bin,
+                         const uint8_t* level, const uint32_t* slot, uint32_t* out,
+                         hipStream_t s);
+
+// library.hip
+size_t library_sort_temp_bytes(int64_t n);
+hipError_t launch_library_sort(int64_t n, const double* pmz, const int8_t* charge,
+                               bool use_charge, void* temp, size_t temp_bytes,
+                               uint32_t* perm_out, double* pmz_out, int8_t* charge_out,
+                               uint32_t* slot_out, hipStream_t s);
+hipError_t launch_gather_rows(int64_t n, uint32_t words, const uint32_t* src,
+                              const uint32_t* orig, uint32_t* dst, hipStream_t s);
+hipError_t launch_window_bounds(const homs_ctx* c, int64_t nq, const double* q_pmz,
+                                const int8_t* q_charge, int32_t kind, double value,
+                                const int8_t* kinds, const double* values, int64_t* lo,
+                                int64_t* hi, hipStream_t s);
+size_t query_sort_temp_bytes(int64_t nq);
+hipError_t launch_query_sort(int64_t nq, const double* q_pmz, const int8_t* q_charge,
+                             bool use_charge, void* temp, size_t temp_bytes,
+                             uint64_t* keys_a, uint64_t* keys_b, uint32_t* perm_a,
+                             uint32_t* perm_b, uint32_t** perm_out, hipStream_t s);
+hipError_t launch_init_keys(int64_t nq, uint64_t* keys, hipStream_t s);
+hipError_t launch_finalize(int64_t nq, const uint64_t* keys, int64_t* idx, int32_t* dist,
+                           hipStream_t s);
+hipError_t launch_debug_distances(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                  const int64_t* lo, const int64_t* hi,
+                                  const int64_t* row_off, int64_t* out_idx, int32_t* out_dist,
+                                  hipStream_t s);
+
+// search_popc.hip
+struct TilePlan {
+    int64_t n_tiles = 0;
+    int64_t max_chunks = 0;
+    int64_t chunk_rows = 0;
+};
+hipError_t launch_tile_bounds(int64_t nq, const uint32_t* qperm, const int64_t* lo,
+                              const int64_t* hi, int tile, int64_t* tile_lo, int64_t* tile_hi,
+                              hipStream_t s);
+hipError_t launch_search_popcount(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                  const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
+                                  const int64_t* tile_lo, const int64_t* tile_hi,
+                                  const TilePlan& plan, uint64_t* keys, hipStream_t s);
+int search_popcount_tile();
+
+}  // namespace homs

@@ -1,0 +1,382 @@
+"""Python binding of libhyperoms (C ABI in include/hyperoms.h).
+
+Argument marshalling only: every step of preprocessing, encoding and search
+runs inside the native library (host C++ for preprocessing and codebook
+generation, HIP kernels for everything on the device). PyTorch supplies
+device memory and the current HIP stream. If the library is not built this
+module raises at import; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyperoms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2211_16422_amd.build` "
+        "(hipcc, gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HOMS_OK = 0
+HOMS_E_INVALID = -1
+HOMS_E_OOM = -2
+HOMS_E_DEVICE = -3
+HOMS_E_STATE = -4
+HOMS_E_UNSUPPORTED = -5
+
+TOL_DA = 0
+TOL_PPM = 1
+
+ENGINE_POPCOUNT = 0
+ENGINE_MFMA_I8 = 1
+ENGINE_MFMA_F8 = 2
+
+
+class HomsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32),
+                ("n_levels", ctypes.c_uint32), ("top_n", ctypes.c_uint32),
+                ("mz_min", ctypes.c_double), ("mz_max", ctypes.c_double),
+                ("bins_per_da", ctypes.c_double), ("noise_frac", ctypes.c_double),
+                ("id_flips", ctypes.c_uint32), ("charge_match", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Window(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("value", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_st = ctypes.c_int32
+
+
+def _sig(name, argtypes, restype=_st):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+_sig("homs_params_default", [ctypes.POINTER(_Params)])
+_sig("homs_num_bins", [ctypes.POINTER(_Params)], _i64)
+_sig("homs_status_string", [_st], ctypes.c_char_p)
+_sig("homs_last_error", [_P], ctypes.c_char_p)
+_sig("homs_preprocess", [ctypes.POINTER(_Params), _i64, _P, _P, _P, _P, _P, _P, _P, _i32])
+_sig("homs_create", [ctypes.POINTER(_Params), _i32, ctypes.POINTER(_P)])
+_sig("homs_destroy", [_P], None)
+_sig("homs_generate_codebook", [ctypes.POINTER(_Params), _P, _P])
+_sig("homs_set_codebook", [_P, _P, _P])
+_sig("homs_get_codebook", [_P, _P, _P])
+_sig("homs_encode_queries", [_P, _i64, _P, _P, _P, _P, _P])
+_sig("homs_encode_library", [_P, _i64, _P, _P, _P, _P, _P, _P])
+_sig("homs_library_size", [_P, ctypes.POINTER(_i64)])
+_sig("homs_library_export", [_P, _P, _P])
+_sig("homs_window_bounds", [_P, _i64, _P, _P, ctypes.POINTER(_Window), _P, _P, _P])
+_sig("homs_search_window", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P])
+_sig("homs_debug_distances", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _P, _P, _P, _P])
+_sig("homs_device_errors", [_P, ctypes.POINTER(ctypes.c_uint32), _P])
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("search_ms", ctypes.c_double), ("encode_ms", ctypes.c_double),
+                ("prep_ms", ctypes.c_double), ("search_launches", ctypes.c_int64),
+                ("encode_launches", ctypes.c_int64)]
+
+
+_sig("homs_profile_enable", [_P, _i32])
+_sig("homs_profile_read", [_P, ctypes.POINTER(_Profile)])
+
+EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_last_error",
+            "homs_preprocess", "homs_create", "homs_destroy", "homs_generate_codebook", "homs_set_codebook",
+            "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
+            "homs_library_size", "homs_library_export", "homs_window_bounds",
+            "homs_search_window", "homs_debug_distances", "homs_device_errors",
+            "homs_profile_enable", "homs_profile_read"]
+
+
+@dataclass(frozen=True)
+class Params:
+    """homs_params (Table 1; Section 4.2 defaults)."""
+
+    dim: int = 8192
+    n_levels: int = 16
+    top_n: int = 50
+    mz_min: float = 101.0
+    mz_max: float = 1500.0
+    bins_per_da: float = 20.0
+    noise_frac: float = 0.01
+    id_flips: int = 0
+    charge_match: bool = True
+    seed: int = 0
+
+    def _c(self) -> _Params:
+        p = _Params()
+        _lib.homs_params_default(ctypes.byref(p))
+        p.dim, p.n_levels, p.top_n = self.dim, self.n_levels, self.top_n
+        p.mz_min, p.mz_max = self.mz_min, self.mz_max
+        p.bins_per_da, p.noise_frac = self.bins_per_da, self.noise_frac
+        p.id_flips, p.charge_match, p.seed = self.id_flips, int(self.charge_match), self.seed
+        return p
+
+    @property
+    def words(self) -> int:
+        return self.dim // 32
+
+
+def last_error(ctx=None) -> str:
+    m = _lib.homs_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(status: int, ctx=None):
+    if status != HOMS_OK:
+        raise HomsError(status, last_error(ctx) or _lib.homs_status_string(status).decode())
+
+
+def num_bins(p: Params) -> int:
+    c = p._c()
+    return int(_lib.homs_num_bins(ctypes.byref(c)))
+
+
+def generate_codebook(p: Params) -> Tuple[np.ndarray, np.ndarray]:
+    """homs_generate_codebook: (ID table [f, D/32], level table [Q, D/32]) on the host."""
+    f = num_bins(p)
+    idt = np.zeros((f, p.words), dtype=np.uint32)
+    lvt = np.zeros((p.n_levels, p.words), dtype=np.uint32)
+    c = p._c()
+    _check(_lib.homs_generate_codebook(ctypes.byref(c), _np_ptr(idt), _np_ptr(lvt)))
+    return idt, lvt
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def preprocess(p: Params, offsets, mz, intensity, n_threads: int = 0
+               ) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """homs_preprocess: raw CSR peaks (host) -> (offsets, bin, level) (host)."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    mz = np.ascontiguousarray(mz, dtype=np.float64)
+    it = np.ascontiguousarray(intensity, dtype=np.float64)
+    n = off.shape[0] - 1
+    cap = max(int(off[-1]), 1)
+    o_off = np.zeros(n + 1, dtype=np.int64)
+    o_bin = np.empty(cap, dtype=np.int32)
+    o_lv = np.empty(cap, dtype=np.uint8)
+    tot = _i64(0)
+    c = p._c()
+    _check(_lib.homs_preprocess(ctypes.byref(c), n, _np_ptr(off), _np_ptr(mz), _np_ptr(it),
+                                _np_ptr(o_off), _np_ptr(o_bin), _np_ptr(o_lv),
+                                ctypes.byref(tot), n_threads))
+    t = tot.value
+    return o_off, o_bin[:t], o_lv[:t]
+
+
+def _stream(dev) -> int:
+    import torch
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _dptr(t, dtype, name: str, device) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, context is on {device}")
+    return t.data_ptr()
+
+
+class Context:
+    """A homs_ctx: codebook, device-resident sorted library, workspace."""
+
+    def __init__(self, params: Params, device: int = 0):
+        import torch
+        self.params = params
+        self.device = torch.device("cuda", device)
+        self.words = params.dim // 32
+        self.n_bins = num_bins(params)
+        h = _P()
+        c = params._c()
+        _check(_lib.homs_create(ctypes.byref(c), device, ctypes.byref(h)))
+        self._h = h
+
+    # --- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.homs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _ck(self, status):
+        _check(status, self._h)
+
+    # --- codebook
+    def get_codebook(self) -> Tuple[np.ndarray, np.ndarray]:
+        idt = np.zeros((self.n_bins, self.words), dtype=np.uint32)
+        lvt = np.zeros((self.params.n_levels, self.words), dtype=np.uint32)
+        self._ck(_lib.homs_get_codebook(self._h, _np_ptr(idt), _np_ptr(lvt)))
+        return idt, lvt
+
+    def set_codebook(self, id_table: Optional[np.ndarray] = None,
+                     level_table: Optional[np.ndarray] = None):
+        a = b = None
+        if id_table is not None:
+            a = np.ascontiguousarray(id_table, dtype=np.uint32)
+            if a.shape != (self.n_bins, self.words):
+                raise ValueError("id table shape")
+        if level_table is not None:
+            b = np.ascontiguousarray(level_table, dtype=np.uint32)
+            if b.shape != (self.params.n_levels, self.words):
+                raise ValueError("level table shape")
+        self._ck(_lib.homs_set_codebook(self._h, _np_ptr(a) if a is not None else None,
+                                        _np_ptr(b) if b is not None else None))
+
+    # --- encoding
+    def encode_queries(self, offsets, bins, levels, out=None):
+        """homs_encode_queries on device CSR tensors -> uint32 [n, D/32] (int32 view)."""
+        import torch
+        n = offsets.shape[0] - 1
+        if out is None:
+            out = torch.empty((n, self.words), dtype=torch.int32, device=self.device)
+        self._ck(_lib.homs_encode_queries(
+            self._h, n, _dptr(offsets, torch.int64, "offsets", self.device),
+            _dptr(bins, torch.int32, "bins", self.device),
+            _dptr(levels, torch.uint8, "levels", self.device),
+            _dptr(out, torch.int32, "out", self.device), _stream(self.device)))
+        return out
+
+    def encode_library(self, offsets, bins, levels, pmz, charge):
+        import torch
+        n = offsets.shape[0] - 1
+        self._ck(_lib.homs_encode_library(
+            self._h, n, _dptr(offsets, torch.int64, "offsets", self.device),
+            _dptr(bins, torch.int32, "bins", self.device),
+            _dptr(levels, torch.uint8, "levels", self.device),
+            _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), _stream(self.device)))
+
+    def library_size(self) -> int:
+        n = _i64(0)
+        self._ck(_lib.homs_library_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def library_export(self):
+        import torch
+        out = torch.empty((self.library_size(), self.words), dtype=torch.int32,
+                          device=self.device)
+        self._ck(_lib.homs_library_export(self._h, _dptr(out, torch.int32, "out", self.device),
+                                          _stream(self.device)))
+        return out
+
+    # --- search
+    @staticmethod
+    def _win(kind: int, value: float) -> _Window:
+        w = _Window()
+        w.kind, w.reserved, w.value = kind, 0, value
+        return w
+
+    def window_bounds(self, pmz, charge, kind=TOL_DA, value=500.0):
+        import torch
+        nq = pmz.shape[0]
+        lo = torch.empty(nq, dtype=torch.int64, device=self.device)
+        hi = torch.empty(nq, dtype=torch.int64, device=self.device)
+        w = self._win(kind, value)
+        self._ck(_lib.homs_window_bounds(
+            self._h, nq, _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(w),
+            _dptr(lo, torch.int64, "lo", self.device), _dptr(hi, torch.int64, "hi", self.device),
+            _stream(self.device)))
+        return lo, hi
+
+    def search_window(self, q_hv, pmz, charge, kind=TOL_DA, value=500.0,
+                      engine=ENGINE_POPCOUNT, out_idx=None, out_dist=None):
+        """homs_search_window -> (library index int64, Hamming distance int32)."""
+        import torch
+        nq = pmz.shape[0]
+        if q_hv.shape != (nq, self.words):
+            raise ValueError("q_hv must be [nq, D/32]")
+        if out_idx is None:
+            out_idx = torch.empty(nq, dtype=torch.int64, device=self.device)
+        if out_dist is None:
+            out_dist = torch.empty(nq, dtype=torch.int32, device=self.device)
+        w = self._win(kind, value)
+        self._ck(_lib.homs_search_window(
+            self._h, nq, _dptr(q_hv, torch.int32, "q_hv", self.device),
+            _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(w), engine,
+            _dptr(out_idx, torch.int64, "out_idx", self.device),
+            _dptr(out_dist, torch.int32, "out_dist", self.device), _stream(self.device)))
+        return out_idx, out_dist
+
+    def debug_distances(self, q_hv, pmz, charge, kind=TOL_DA, value=500.0):
+        """All candidates with distances: (row_off, lib index, dist) in sorted order."""
+        import torch
+        lo, hi = self.window_bounds(pmz, charge, kind, value)
+        cnt = (hi - lo)
+        row_off = torch.zeros(pmz.shape[0] + 1, dtype=torch.int64, device=self.device)
+        torch.cumsum(cnt, 0, out=row_off[1:])
+        tot = int(row_off[-1].item())
+        idx = torch.empty(max(tot, 1), dtype=torch.int64, device=self.device)
+        dist = torch.empty(max(tot, 1), dtype=torch.int32, device=self.device)
+        w = self._win(kind, value)
+        self._ck(_lib.homs_debug_distances(
+            self._h, pmz.shape[0], _dptr(q_hv, torch.int32, "q_hv", self.device),
+            _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(w),
+            _dptr(row_off, torch.int64, "row_off", self.device),
+            _dptr(idx, torch.int64, "idx", self.device),
+            _dptr(dist, torch.int32, "dist", self.device), _stream(self.device)))
+        return row_off, idx[:tot], dist[:tot]
+
+    def profile_enable(self, on: bool = True):
+        self._ck(_lib.homs_profile_enable(self._h, int(on)))
+
+    def profile_read(self) -> dict:
+        p = _Profile()
+        self._ck(_lib.homs_profile_read(self._h, ctypes.byref(p)))
+        return {"search_ms": p.search_ms, "encode_ms": p.encode_ms, "prep_ms": p.prep_ms,
+                "search_launches": p.search_launches, "encode_launches": p.encode_launches}
+
+    def device_errors(self) -> int:
+        f = ctypes.c_uint32(0)
+        self._ck(_lib.homs_device_errors(self._h, ctypes.byref(f), _stream(self.device)))
+        return f.value
+
+
+def to_device_csr(off, bins, levels, device):
+    """Host CSR (numpy) -> device tensors for the encode entry points."""
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).to(device),
+            torch.from_numpy(np.ascontiguousarray(bins, dtype=np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(levels, dtype=np.uint8)).to(device))

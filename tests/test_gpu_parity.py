@@ -1,0 +1,204 @@
+"""Parity of the HIP path (through the C ABI) with the oracle on the small
+workload: every encoded bit, every candidate window, every in-window
+distance and every top-1 (index, distance) must be identical."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
+
+import oracle  # noqa: E402
+from synth import WORKLOADS, make_workload, subset  # noqa: E402
+
+
+def _h():
+    import paper_2211_16422_amd.hyperoms as h
+    return h
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda:0")
+
+
+def _np_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+class Setup:
+    """Tiny workload encoded by both sides, each from the raw spectra."""
+
+    def __init__(self, dim=2048, n_ref=2000, n_query=200, seed=0, kind=0, value=500.0):
+        h = _h()
+        self.g = make_workload(WORKLOADS["tiny"], n_ref=n_ref, n_query=n_query, seed=seed)
+        self.op = oracle.Params(dim=dim)
+        self.hp = h.Params(dim=dim)
+        idt, lvt = oracle.codebook(self.op)
+        lib, q = self.g.library, self.g.queries
+        self.o_lib = oracle.encode_raw(self.op, idt, lvt, lib)
+        self.o_q = oracle.encode_raw(self.op, idt, lvt, q)
+        self.ctx = h.Context(self.hp)
+        lo, lb, ll = h.preprocess(self.hp, lib.offsets, lib.mz, lib.intensity)
+        qo, qb, ql = h.preprocess(self.hp, q.offsets, q.mz, q.intensity)
+        self.lib_csr = h.to_device_csr(lo, lb, ll, "cuda:0")
+        self.q_csr = h.to_device_csr(qo, qb, ql, "cuda:0")
+        self.ctx.encode_library(*self.lib_csr, _dev(lib.pmz), _dev(lib.charge))
+        self.q_hv = self.ctx.encode_queries(*self.q_csr)
+        self.q_pmz = _dev(q.pmz)
+        self.q_ch = _dev(q.charge)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    s = Setup()
+    yield s
+    s.ctx.close()
+
+
+def test_codebook_matches_oracle(tiny):
+    idt, lvt = tiny.ctx.get_codebook()
+    o_id, o_lv = oracle.codebook(tiny.op)
+    assert np.array_equal(idt, o_id) and np.array_equal(lvt, o_lv)
+
+
+def test_encode_every_bit(tiny):
+    import torch
+    torch.cuda.synchronize()
+    assert np.array_equal(_np_u32(tiny.q_hv), tiny.o_q)
+    lib = _np_u32(tiny.ctx.library_export())
+    assert np.array_equal(lib, tiny.o_lib)
+    assert tiny.ctx.device_errors() == 0
+
+
+def test_window_counts(tiny):
+    lo, hi = tiny.ctx.window_bounds(tiny.q_pmz, tiny.q_ch)
+    cnt = (hi - lo).cpu().numpy()
+    g = tiny.g
+    want = oracle.window_counts(g.library.pmz, g.library.charge, g.queries.pmz, g.queries.charge)
+    assert np.array_equal(cnt, want)
+
+
+def test_every_distance(tiny):
+    g = tiny.g
+    row, idx, dist = tiny.ctx.debug_distances(tiny.q_hv, tiny.q_pmz, tiny.q_ch)
+    row, idx, dist = row.cpu().numpy(), idx.cpu().numpy(), dist.cpu().numpy()
+    o_row, o_idx, o_dist = oracle.window_distances(tiny.op, tiny.o_lib, g.library.pmz,
+                                                   g.library.charge, tiny.o_q, g.queries.pmz,
+                                                   g.queries.charge)
+    assert np.array_equal(row, o_row)
+    for q in range(g.queries.n):
+        a, b = row[q], row[q + 1]
+        order = np.argsort(idx[a:b], kind="stable")
+        assert np.array_equal(idx[a:b][order], o_idx[a:b])
+        assert np.array_equal(dist[a:b][order], o_dist[a:b])
+
+
+@pytest.mark.parametrize("kind,value", [(0, 500.0), (1, 20.0), (0, 0.0), (0, 5.0)])
+def test_top1(tiny, kind, value):
+    g = tiny.g
+    idx, dist = tiny.ctx.search_window(tiny.q_hv, tiny.q_pmz, tiny.q_ch, kind=kind, value=value)
+    o_idx, o_dist = oracle.search(tiny.op, tiny.o_lib, g.library.pmz, g.library.charge,
+                                  tiny.o_q, g.queries.pmz, g.queries.charge, kind, value)
+    assert np.array_equal(idx.cpu().numpy(), o_idx)
+    assert np.array_equal(dist.cpu().numpy(), o_dist)
+
+
+def test_top1_d8192_ragged():
+    """D = 8192 (Section 4.2) with a query count that leaves a ragged tile."""
+    s = Setup(dim=8192, n_ref=1500, n_query=333, seed=3)
+    g = s.g
+    try:
+        assert np.array_equal(_np_u32(s.q_hv), s.o_q)
+        idx, dist = s.ctx.search_window(s.q_hv, s.q_pmz, s.q_ch)
+        o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
+                                      g.queries.pmz, g.queries.charge)
+        assert np.array_equal(idx.cpu().numpy(), o_idx)
+        assert np.array_equal(dist.cpu().numpy(), o_dist)
+    finally:
+        s.ctx.close()
+
+
+def test_exact_copies_and_duplicates(tiny):
+    """Queries that copy library spectra: distance 0; a decoy shares its
+    reference's pmz and charge, and exact duplicates go to the lowest index."""
+    h = _h()
+    g = tiny.g
+    rows = np.array([0, 5, 1999, 2000, 2500, 3999])
+    q = subset(g.library, rows)
+    qo, qb, ql = h.preprocess(tiny.hp, q.offsets, q.mz, q.intensity)
+    qhv = tiny.ctx.encode_queries(*h.to_device_csr(qo, qb, ql, "cuda:0"))
+    idx, dist = tiny.ctx.search_window(qhv, _dev(q.pmz), _dev(q.charge))
+    o_q = tiny.o_lib[rows]
+    o_idx, o_dist = oracle.search(tiny.op, tiny.o_lib, g.library.pmz, g.library.charge, o_q,
+                                  q.pmz, q.charge)
+    assert np.array_equal(idx.cpu().numpy(), o_idx)
+    assert np.all(dist.cpu().numpy() == 0)
+
+
+def test_edge_cases(tiny):
+    """Empty windows (-1, -1): NaN precursor, a charge absent from the
+    library, a precursor far outside the library range; nq = 0."""
+    import torch
+    qhv = tiny.q_hv[:4].contiguous()
+    pmz = _dev(np.array([np.nan, 900.0, 5000.0, 900.0]))
+    ch = _dev(np.array([2, 9, 2, 3], dtype=np.int8))
+    idx, dist = tiny.ctx.search_window(qhv, pmz, ch)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert idx[:3].tolist() == [-1, -1, -1] and dist[:3].tolist() == [-1, -1, -1]
+    assert idx[3] >= 0
+    e_idx, e_dist = tiny.ctx.search_window(qhv[:0], pmz[:0], ch[:0])
+    assert e_idx.numel() == 0 and e_dist.numel() == 0
+    torch.cuda.synchronize()
+
+
+def test_custom_codebook_ties():
+    """A codebook in which different spectra bind to the same vectors gives
+    exact distance ties on the device; the lowest library index must win."""
+    h = _h()
+    D = 2048
+    hp = h.Params(dim=D)
+    op = oracle.Params(dim=D)
+    rng = np.random.default_rng(1)
+    f = h.num_bins(hp)
+    idt = np.repeat(rng.integers(0, 2**32, size=(4, D // 32), dtype=np.uint32), f // 4 + 1,
+                    axis=0)[:f].copy()
+    lvt = rng.integers(0, 2**32, size=(16, D // 32), dtype=np.uint32)
+    lvt[8:] = lvt[:8]
+    g = make_workload(WORKLOADS["tiny"], n_ref=400, n_query=64, seed=5)
+    with h.Context(hp) as ctx:
+        ctx.set_codebook(idt, lvt)
+        lo, lb, ll = h.preprocess(hp, g.library.offsets, g.library.mz, g.library.intensity)
+        qo, qb, ql = h.preprocess(hp, g.queries.offsets, g.queries.mz, g.queries.intensity)
+        ctx.encode_library(*h.to_device_csr(lo, lb, ll, "cuda:0"), _dev(g.library.pmz),
+                           _dev(g.library.charge))
+        qhv = ctx.encode_queries(*h.to_device_csr(qo, qb, ql, "cuda:0"))
+        idx, dist = ctx.search_window(qhv, _dev(g.queries.pmz), _dev(g.queries.charge))
+        o_lib = oracle.encode(op, idt, lvt, lo, lb, ll)
+        o_q = oracle.encode(op, idt, lvt, qo, qb, ql)
+        assert np.array_equal(_np_u32(qhv), o_q)
+        o_idx, o_dist = oracle.search(op, o_lib, g.library.pmz, g.library.charge, o_q,
+                                      g.queries.pmz, g.queries.charge)
+        # the codebook makes many library vectors identical: ties are real
+        assert len(np.unique(o_lib, axis=0)) < len(o_lib)
+        assert np.array_equal(idx.cpu().numpy(), o_idx)
+        assert np.array_equal(dist.cpu().numpy(), o_dist)
+
+
+def test_encode_range_error_flag():
+    """A bin outside [0, f) is skipped and raises the device error flag."""
+    import torch
+    h = _h()
+    hp = h.Params(dim=512)
+    with h.Context(hp) as ctx:
+        off = torch.tensor([0, 2], dtype=torch.int64, device="cuda:0")
+        b = torch.tensor([3, 10**7], dtype=torch.int32, device="cuda:0")
+        lv = torch.tensor([1, 1], dtype=torch.uint8, device="cuda:0")
+        ctx.encode_queries(off, b, lv)
+        assert ctx.device_errors() & 1
+        assert ctx.device_errors() == 0
+        with pytest.raises(h.HomsError):
+            ctx.encode_library(off, b, lv, torch.zeros(1, dtype=torch.float64, device="cuda:0"),
+                               torch.zeros(1, dtype=torch.int8, device="cuda:0"))
