@@ -31,6 +31,19 @@ if ROOT not in sys.path:
 METRIC = "query-ref Hamming comparisons/s and queries/s at ±500 Da, D=8192"
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz, 32-bit ops
 
+# HBM bytes per launch of the search kernel on the default large workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
+# (profiles/search_popcount_large.md). Valid only while the kernel source has
+# the hash it was measured on.
+MEASURED_TRAFFIC = {"723757d434de86f7": 4.651e12}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2211_16422_amd", "csrc", "search_popc.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
 
 def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -48,6 +61,9 @@ def main():
                     help="queries in the oracle's timed sample (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baseline (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run one device-to-device copy of BYTES bytes (a reference "
+                         "kernel for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -103,6 +119,16 @@ def main():
         ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, h.ENGINE_POPCOUNT,
                           out_idx=out_idx, out_dist=out_dist)
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {4 * n} bytes read and written")
+        del src, dst
+
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -127,8 +153,10 @@ def main():
     search_ms = prof["search_ms"] / max(prof["search_launches"], 1)
     ops_per_launch = 2.0 * words * pairs  # v_xor_b32 + v_bcnt_u32_b32 per word per pair
     achieved = ops_per_launch / (search_ms * 1e-3) / 1e12
+    default_shape = args.n_ref is None and args.n_query is None and w.name == "large"
+    traffic = MEASURED_TRAFFIC.get(kernel_source_hash()) if default_shape else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": "search_popcount_kernel", "kernel_ms": round(search_ms, 3),
                 "ops_per_pair": 2 * words}
 

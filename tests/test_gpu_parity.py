@@ -154,19 +154,22 @@ def test_edge_cases(tiny):
     torch.cuda.synchronize()
 
 
-def test_custom_codebook_ties():
-    """A codebook in which different spectra bind to the same vectors gives
-    exact distance ties on the device; the lowest library index must win."""
+@pytest.mark.parametrize("distinct", [1, 2])
+def test_custom_codebook_ties(distinct):
+    """Codebooks whose position vectors take only `distinct` values and whose
+    level vectors are all equal make many library vectors identical (with
+    one value, every non-empty spectrum encodes to the same vector by the
+    majority rule), so exact distance ties are everywhere on the device; the
+    lowest library index must win each of them."""
     h = _h()
     D = 2048
     hp = h.Params(dim=D)
     op = oracle.Params(dim=D)
     rng = np.random.default_rng(1)
     f = h.num_bins(hp)
-    idt = np.repeat(rng.integers(0, 2**32, size=(4, D // 32), dtype=np.uint32), f // 4 + 1,
-                    axis=0)[:f].copy()
-    lvt = rng.integers(0, 2**32, size=(16, D // 32), dtype=np.uint32)
-    lvt[8:] = lvt[:8]
+    base = rng.integers(0, 2**32, size=(distinct, D // 32), dtype=np.uint32)
+    idt = base[(np.arange(f) * distinct) // f].copy()
+    lvt = np.repeat(rng.integers(0, 2**32, size=(1, D // 32), dtype=np.uint32), 16, axis=0)
     g = make_workload(WORKLOADS["tiny"], n_ref=400, n_query=64, seed=5)
     with h.Context(hp) as ctx:
         ctx.set_codebook(idt, lvt)
