@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "query-ref Hamming comparisons/s and queries/s at ±500 Da, D=8192"
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz, 32-bit ops
+MFMA_PEAK_TOPS = 5000.0  # dense fp8 / int8 matrix peak of MI355X, TFLOP/s (TOP/s)
 
 # HBM bytes per launch of the search kernel on the default large workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
@@ -61,6 +62,8 @@ def main():
                     help="queries in the oracle's timed sample (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baseline (for profiler runs)")
+    ap.add_argument("--skip-mfma", action="store_true",
+                    help="do not time the matrix-core (precision) form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES bytes (a reference "
                          "kernel for scaling hardware byte counters)")
@@ -162,6 +165,37 @@ def main():
 
     res_idx = out_idx.cpu().numpy()
     res_dist = out_dist.cpu().numpy()
+
+    # precision form: the same search on matrix cores (fp8 e4m3 and int8 +-1)
+    forms = {}
+    if not args.skip_mfma:
+        for name, engine in (("mfma_fp8", h.ENGINE_MFMA_F8), ("mfma_int8", h.ENGINE_MFMA_I8)):
+            m_idx = torch.empty_like(out_idx)
+            m_dist = torch.empty_like(out_dist)
+            ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine, m_idx, m_dist)
+            torch.cuda.synchronize()
+            ctx.profile_enable(True)
+            ctx.profile_read()
+            reps = max(1, args.steps)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine, m_idx, m_dist)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            pm = ctx.profile_read()
+            ctx.profile_enable(False)
+            kms = pm["search_ms"] / max(pm["search_launches"], 1)
+            same = bool(np.array_equal(m_idx.cpu().numpy(), res_idx) and
+                        np.array_equal(m_dist.cpu().numpy(), res_dist))
+            tops = 2.0 * w.dim * pairs / (kms * 1e-3) / 1e12
+            forms[name] = {"comparisons_per_s": pairs * reps / el, "kernel_ms": round(kms, 3),
+                           "achieved": round(tops, 1), "peak": MFMA_PEAK_TOPS,
+                           "unit": "TOP/s", "frac": round(tops / MFMA_PEAK_TOPS, 4),
+                           "vs_popcount_valu_roofline": round(
+                               pairs / (kms * 1e-3) / (VALU_PEAK_TOPS * 1e12 / (2 * words)), 3),
+                           "bit_exact_vs_popcount": same}
+            log(f"{name}: search kernel {kms:.2f} ms ({tops:.0f} TOP/s, "
+                f"{tops / MFMA_PEAK_TOPS:.1%} of peak), identical to popcount: {same}")
     cpu = None
     parity = None
     if args.cpu_sample > 0 and not args.profile_only:
@@ -182,6 +216,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
+        "precision_form": forms,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

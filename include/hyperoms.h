@@ -91,8 +91,10 @@ typedef struct homs_window {
 /* Search engines for homs_search_window. POPCOUNT: XOR + population count
  * on packed words (Section 3.4 with the bit packing of Section 4.1).
  * MFMA_I8 / MFMA_F8: the same distances as H = (D - <x, y>) / 2 of the
- * bipolar vectors, contracted on matrix cores with int8 (int32 accumulate)
- * or fp8 e4m3 (fp32 accumulate) operands; exact for D <= 16384. */
+ * bipolar vectors (Section 3.3), contracted on matrix cores with int8 +-1
+ * (int32 accumulate) or fp8 e4m3 +-1.0 (fp32 accumulate) operands expanded
+ * from the packed bits on the fly. Every partial sum is an integer of
+ * magnitude <= D <= 32768, so all engines return identical results. */
 #define HOMS_ENGINE_POPCOUNT 0
 #define HOMS_ENGINE_MFMA_I8 1
 #define HOMS_ENGINE_MFMA_F8 2
@@ -215,6 +217,60 @@ homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv
                                const double *d_q_pmz, const int8_t *d_q_charge,
                                const homs_window *win, int32_t engine, int64_t *d_out_idx,
                                int32_t *d_out_dist, void *stream);
+
+/*
+ * Tunables of homs_search_batched, chosen by homs_autotune_batched or set by
+ * the caller.
+ *  narrow_max    a query with at most this many candidates is scored on its
+ *                own by one wave (one candidate per lane); larger windows are
+ *                scored in 256-query tiles sharing one candidate range.
+ *  chunk_rows    candidate rows per tile work item.
+ *  narrow_group  narrow queries per work item, a multiple of 4 (>= 4).
+ *  grid          workgroups of the persistent kernel (1..65535).
+ *  bucket_da     precursor bucket width (Da) used to order queries into tiles.
+ */
+typedef struct homs_batched_config {
+    uint32_t narrow_max;
+    uint32_t chunk_rows;
+    uint32_t narrow_group;
+    uint32_t grid;
+    double bucket_da;
+} homs_batched_config;
+homs_status homs_batched_config_get(const homs_ctx *ctx, homs_batched_config *out);
+homs_status homs_batched_config_set(homs_ctx *ctx, const homs_batched_config *cfg);
+
+/*
+ * Search of a mixed query stream (Section 3.4, cascade search: narrow
+ * standard windows and wide open windows, Table 1) in one persistent
+ * launch: per query q the window is d_kinds[q] (HOMS_TOL_DA or
+ * HOMS_TOL_PPM) with tolerance d_values[q]. Results are defined exactly as
+ * for homs_search_window. Every step runs on the device with a fixed launch
+ * shape and no host synchronisation; with use_graph = 1 the batch is
+ * captured into a hipGraph on first use and replayed while nq, every
+ * pointer argument, the configuration and the library stay the same (a
+ * change re-captures). Asynchronous on `stream`; grows the workspace (a
+ * device allocation) on first use of a larger nq. Calls on one context must
+ * not overlap.
+ */
+homs_status homs_search_batched(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                                const double *d_q_pmz, const int8_t *d_q_charge,
+                                const int8_t *d_kinds, const double *d_values,
+                                int64_t *d_out_idx, int32_t *d_out_dist, int32_t use_graph,
+                                void *stream);
+
+/*
+ * Autotuner of the batched search: times candidate configurations on the
+ * given batch (coordinate descent over chunk_rows, grid, narrow_max and
+ * narrow_group from the current configuration, `reps` timed runs each after
+ * one warm-up), keeps the fastest in the context and returns it with its
+ * time per batch in *best_ms. The outputs hold the last run's (identical)
+ * results. Synchronous.
+ */
+homs_status homs_autotune_batched(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                                  const double *d_q_pmz, const int8_t *d_q_charge,
+                                  const int8_t *d_kinds, const double *d_values,
+                                  int64_t *d_out_idx, int32_t *d_out_dist, int32_t reps,
+                                  homs_batched_config *best, double *best_ms, void *stream);
 
 /*
  * Every candidate of every query with its Hamming distance (test support).

@@ -135,11 +135,14 @@ void free_library(homs::Library& L)
     L = homs::Library{};
 }
 
+void drop_graph(homs_ctx* c);
+
 // Grows the context's workspace to at least `bytes` (synchronising first).
 homs_status ensure_workspace(homs_ctx* c, size_t bytes, hipStream_t s)
 {
     if (c->ws.bytes >= bytes) return HOMS_OK;
     HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    drop_graph(c);
     if (c->ws.ptr) (void)hipFree(c->ws.ptr);
     c->ws = homs::Workspace{};
     const size_t want = bytes + bytes / 4;
@@ -364,6 +367,8 @@ void homs_destroy(homs_ctx* c)
     if (c->d_level) (void)hipFree(c->d_level);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->ws.ptr) (void)hipFree(c->ws.ptr);
+    drop_graph(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& sp : c->prof.pending) {
         c->prof.pool.push_back(sp.a);
         c->prof.pool.push_back(sp.b);
@@ -385,7 +390,10 @@ homs_status homs_set_codebook(homs_ctx* c, const uint32_t* h_id, const uint32_t*
         HIP_TRY(c, hipMemcpy(c->d_level, h_level, (size_t)c->p.n_levels * c->words * 4,
                              hipMemcpyHostToDevice),
                 "hipMemcpy(level table)");
-    if (h_id || h_level) c->lib_valid = false;
+    if (h_id || h_level) {
+        c->lib_valid = false;
+        drop_graph(c);
+    }
     return HOMS_OK;
 }
 
@@ -435,6 +443,7 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
     free_library(c->lib);
     c->lib_valid = false;
+    drop_graph(c);
     if (n == 0) {
         c->lib_valid = true;
         return HOMS_OK;
@@ -447,7 +456,10 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     hipError_t e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
     if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
-    if (e == hipSuccess) e = hipMalloc(&L.orig, (size_t)n * 4);
+    // the MFMA epilogue reads library indices in groups past the last row
+    const size_t orig_pad = (size_t)homs::search_mfma_row_pad();
+    if (e == hipSuccess) e = hipMalloc(&L.orig, ((size_t)n + orig_pad) * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(L.orig + n, 0, orig_pad * 4, s);
     if (e == hipSuccess) e = hipMalloc(&slot, (size_t)n * 4);
     if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
@@ -529,11 +541,10 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist)
         return fail(c, HOMS_E_INVALID, "NULL device pointer");
     if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
-    if (engine != HOMS_ENGINE_POPCOUNT)
-        return fail(c, HOMS_E_UNSUPPORTED, "MFMA engines are not built yet");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    const int tile = homs::search_popcount_tile();
+    const int tile = engine == HOMS_ENGINE_POPCOUNT ? homs::search_popcount_tile()
+                                                    : homs::search_mfma_tile();
     if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, tile), s)) return st;
     SearchScratch w = carve(c->ws.ptr, nq, tile);
 
@@ -550,15 +561,250 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
     homs::TilePlan plan;
     hipEvent_t e1 = prof_mark(c, s);
-    HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, w.lo, w.hi, w.tile_lo, w.tile_hi,
-                                            plan, w.keys, s),
-            "search kernel");
+    if (engine == HOMS_ENGINE_POPCOUNT)
+        HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, w.lo, w.hi, w.tile_lo,
+                                                w.tile_hi, plan, w.keys, s),
+                "search kernel");
+    else
+        HIP_TRY(c, homs::launch_search_mfma(c, engine == HOMS_ENGINE_MFMA_I8 ? 0 : 1, nq, d_q_hv,
+                                            qperm, w.lo, w.hi, w.tile_lo, w.tile_hi, w.keys, s),
+                "MFMA search kernel");
     hipEvent_t e2 = prof_mark(c, s);
     HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");
     hipEvent_t e3 = prof_mark(c, s);
     prof_span(c, e0, e1, homs::kProfPrep);
     prof_span(c, e1, e2, homs::kProfSearch);
     prof_span(c, e2, e3, homs::kProfPrep);
+    return HOMS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool batched_config_valid(const homs_batched_config* b, std::string* why)
+{
+    if (!b) {
+        *why = "config is NULL";
+        return false;
+    }
+    if (b->chunk_rows < 32 || b->chunk_rows > (1u << 24)) {
+        *why = "chunk_rows must be in [32, 2^24]";
+        return false;
+    }
+    if (b->narrow_group < 4 || b->narrow_group % 4 != 0 || b->narrow_group > 4096) {
+        *why = "narrow_group must be a multiple of 4 in [4, 4096]";
+        return false;
+    }
+    if (b->grid < 1 || b->grid > 65535) {
+        *why = "grid must be in [1, 65535]";
+        return false;
+    }
+    if (!std::isfinite(b->bucket_da) || !(b->bucket_da > 0.0)) {
+        *why = "bucket_da must be finite and > 0";
+        return false;
+    }
+    return true;
+}
+
+homs::BatchedConfig to_internal(const homs_batched_config& b)
+{
+    homs::BatchedConfig c;
+    c.narrow_max = b.narrow_max;
+    c.chunk_rows = b.chunk_rows;
+    c.narrow_group = b.narrow_group;
+    c.grid = b.grid;
+    c.bucket_da = b.bucket_da;
+    return c;
+}
+
+homs_batched_config to_public(const homs::BatchedConfig& c)
+{
+    homs_batched_config b;
+    b.narrow_max = c.narrow_max;
+    b.chunk_rows = c.chunk_rows;
+    b.narrow_group = c.narrow_group;
+    b.grid = c.grid;
+    b.bucket_da = c.bucket_da;
+    return b;
+}
+
+void drop_graph(homs_ctx* c)
+{
+    if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+    if (c->graph.graph) (void)hipGraphDestroy(c->graph.graph);
+    c->graph = homs::GraphCache{};
+}
+
+homs_status batched_check(homs_ctx* c, int64_t nq, const uint32_t* q_hv, const double* q_pmz,
+                          const int8_t* q_charge, const int8_t* kinds, const double* values,
+                          int64_t* out_idx, int32_t* out_dist)
+{
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!q_hv || !q_pmz || !q_charge || !kinds || !values || !out_idx || !out_dist)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    return HOMS_OK;
+}
+
+// One batched search, eager or through the cached graph.
+homs_status run_batched(homs_ctx* c, const homs::BatchedConfig& cfg, int64_t nq,
+                        const uint32_t* q_hv, const double* q_pmz, const int8_t* q_charge,
+                        const int8_t* kinds, const double* values, int64_t* out_idx,
+                        int32_t* out_dist, bool use_graph, hipStream_t s)
+{
+    if (homs_status st = ensure_workspace(c, homs::batched_scratch_bytes(nq), s)) return st;
+    hipEvent_t e0 = prof_mark(c, s);
+    if (!use_graph) {
+        HIP_TRY(c, homs::launch_search_batched(c, cfg, c->ws.ptr, nq, q_hv, q_pmz, q_charge, kinds,
+                                               values, out_idx, out_dist, s),
+                "batched search");
+    } else {
+        std::vector<uintptr_t> key = {
+            (uintptr_t)nq,        (uintptr_t)q_hv,       (uintptr_t)q_pmz,
+            (uintptr_t)q_charge,  (uintptr_t)kinds,      (uintptr_t)values,
+            (uintptr_t)out_idx,   (uintptr_t)out_dist,   (uintptr_t)c->ws.ptr,
+            (uintptr_t)c->lib.hv, (uintptr_t)c->lib.n,   (uintptr_t)cfg.narrow_max,
+            (uintptr_t)cfg.chunk_rows, (uintptr_t)cfg.narrow_group, (uintptr_t)cfg.grid,
+            (uintptr_t)(cfg.bucket_da * 1e9)};
+        if (!c->graph.exec || c->graph.key != key) {
+            drop_graph(c);
+            if (!c->capture_stream)
+                HIP_TRY(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking),
+                        "hipStreamCreateWithFlags");
+            HIP_TRY(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal),
+                    "hipStreamBeginCapture");
+            hipError_t le = homs::launch_search_batched(c, cfg, c->ws.ptr, nq, q_hv, q_pmz,
+                                                        q_charge, kinds, values, out_idx,
+                                                        out_dist, c->capture_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t ce = hipStreamEndCapture(c->capture_stream, &graph);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(c, le != hipSuccess ? le : ce, "capturing the batched search");
+            }
+            hipGraphExec_t exec = nullptr;
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(c, ie, "hipGraphInstantiate");
+            }
+            c->graph.graph = graph;
+            c->graph.exec = exec;
+            c->graph.key = key;
+        }
+        HIP_TRY(c, hipGraphLaunch(c->graph.exec, s), "hipGraphLaunch");
+    }
+    prof_span(c, e0, prof_mark(c, s), homs::kProfSearch);
+    return HOMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+homs_status homs_batched_config_get(const homs_ctx* c, homs_batched_config* out)
+{
+    if (!c || !out) return fail(nullptr, HOMS_E_INVALID, "NULL argument");
+    *out = to_public(c->batched);
+    return HOMS_OK;
+}
+
+homs_status homs_batched_config_set(homs_ctx* c, const homs_batched_config* cfg)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!batched_config_valid(cfg, &why)) return fail(c, HOMS_E_INVALID, why);
+    c->batched = to_internal(*cfg);
+    return HOMS_OK;
+}
+
+homs_status homs_search_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                                const double* d_q_pmz, const int8_t* d_q_charge,
+                                const int8_t* d_kinds, const double* d_values,
+                                int64_t* d_out_idx, int32_t* d_out_dist, int32_t use_graph,
+                                void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (homs_status s = batched_check(c, nq, d_q_hv, d_q_pmz, d_q_charge, d_kinds, d_values,
+                                      d_out_idx, d_out_dist))
+        return s;
+    if (nq == 0) return HOMS_OK;
+    DeviceGuard g(c->device);
+    return run_batched(c, c->batched, nq, d_q_hv, d_q_pmz, d_q_charge, d_kinds, d_values,
+                       d_out_idx, d_out_dist, use_graph != 0, (hipStream_t)stream);
+}
+
+homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                                  const double* d_q_pmz, const int8_t* d_q_charge,
+                                  const int8_t* d_kinds, const double* d_values,
+                                  int64_t* d_out_idx, int32_t* d_out_dist, int32_t reps,
+                                  homs_batched_config* best, double* best_ms, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (homs_status s = batched_check(c, nq, d_q_hv, d_q_pmz, d_q_charge, d_kinds, d_values,
+                                      d_out_idx, d_out_dist))
+        return s;
+    if (reps < 1 || reps > 1000) return fail(c, HOMS_E_INVALID, "reps must be in [1, 1000]");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool prof = c->prof.on;
+    c->prof.on = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&t0), "hipEventCreate");
+    HIP_TRY(c, hipEventCreate(&t1), "hipEventCreate");
+    auto time_cfg = [&](const homs::BatchedConfig& cfg, double* ms) -> homs_status {
+        if (nq == 0) {
+            *ms = 0.0;
+            return HOMS_OK;
+        }
+        if (homs_status st = run_batched(c, cfg, nq, d_q_hv, d_q_pmz, d_q_charge, d_kinds,
+                                         d_values, d_out_idx, d_out_dist, false, s))
+            return st;
+        HIP_TRY(c, hipEventRecord(t0, s), "hipEventRecord");
+        for (int r = 0; r < reps; ++r)
+            if (homs_status st = run_batched(c, cfg, nq, d_q_hv, d_q_pmz, d_q_charge, d_kinds,
+                                             d_values, d_out_idx, d_out_dist, false, s))
+                return st;
+        HIP_TRY(c, hipEventRecord(t1, s), "hipEventRecord");
+        HIP_TRY(c, hipEventSynchronize(t1), "hipEventSynchronize");
+        float f = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&f, t0, t1), "hipEventElapsedTime");
+        *ms = (double)f / reps;
+        return HOMS_OK;
+    };
+    homs::BatchedConfig cur = c->batched;
+    double cur_ms = 0.0;
+    homs_status st = time_cfg(cur, &cur_ms);
+    const uint32_t chunks[] = {1024, 2048, 4096, 8192};
+    const uint32_t grids[] = {512, 1024, 2048, 4096};
+    const uint32_t narrows[] = {256, 1024, 4096};
+    const uint32_t groups[] = {16, 32, 64};
+    auto sweep = [&](auto set, const uint32_t* vals, int n) {
+        for (int i = 0; i < n && st == HOMS_OK; ++i) {
+            homs::BatchedConfig cand = cur;
+            set(cand, vals[i]);
+            double ms = 0.0;
+            st = time_cfg(cand, &ms);
+            if (st == HOMS_OK && ms < cur_ms) {
+                cur = cand;
+                cur_ms = ms;
+            }
+        }
+    };
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.chunk_rows = v; }, chunks, 4);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.grid = v; }, grids, 4);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_max = v; }, narrows, 3);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_group = v; }, groups, 3);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    c->prof.on = prof;
+    if (st != HOMS_OK) return st;
+    c->batched = cur;
+    if (best) *best = to_public(cur);
+    if (best_ms) *best_ms = cur_ms;
     return HOMS_OK;
 }
 

@@ -28,6 +28,22 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Tunables of the batched persistent search (homs_batched_config).
+struct BatchedConfig {
+    uint32_t narrow_max = 1024;   // windows up to this size are scored per query
+    uint32_t chunk_rows = 2048;   // candidate rows per wide work item
+    uint32_t narrow_group = 32;   // narrow queries per work item (multiple of 4)
+    uint32_t grid = 1024;         // persistent workgroups
+    double bucket_da = 0.5;       // precursor bucket width for query ordering
+};
+
+// A captured batched search, replayed while its arguments stay the same.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<uintptr_t> key;
+};
+
 // Event-based kernel timing (homs_profile_*).
 enum ProfKind { kProfSearch = 0, kProfEncode = 1, kProfPrep = 2 };
 struct Profiler {
@@ -56,6 +72,9 @@ struct homs_ctx {
     bool lib_valid = false;
     homs::Workspace ws;
     homs::Profiler prof;
+    homs::BatchedConfig batched;
+    homs::GraphCache graph;
+    hipStream_t capture_stream = nullptr;
     bool dead = false;
     std::string err;
 };
@@ -108,5 +127,21 @@ hipError_t launch_search_popcount(const homs_ctx* c, int64_t nq, const uint32_t*
                                   const int64_t* tile_lo, const int64_t* tile_hi,
                                   const TilePlan& plan, uint64_t* keys, hipStream_t s);
 int search_popcount_tile();
+
+// search_batched.hip
+size_t batched_scratch_bytes(int64_t nq);
+hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, void* scratch,
+                                 int64_t nq, const uint32_t* q_hv, const double* q_pmz,
+                                 const int8_t* q_charge, const int8_t* kinds,
+                                 const double* values, int64_t* out_idx, int32_t* out_dist,
+                                 hipStream_t s);
+
+// search_mfma.hip (fmt 0: int8, 1: fp8 e4m3)
+int search_mfma_tile();
+int64_t search_mfma_row_pad();  // rows of padding the library's orig array needs
+hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint32_t* q_hv,
+                              const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
+                              const int64_t* tile_lo, const int64_t* tile_hi, uint64_t* keys,
+                              hipStream_t s);
 
 }  // namespace homs

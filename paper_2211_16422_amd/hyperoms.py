@@ -102,12 +102,27 @@ class _Profile(ctypes.Structure):
 _sig("homs_profile_enable", [_P, _i32])
 _sig("homs_profile_read", [_P, ctypes.POINTER(_Profile)])
 
+
+class _BatchedConfig(ctypes.Structure):
+    _fields_ = [("narrow_max", ctypes.c_uint32), ("chunk_rows", ctypes.c_uint32),
+                ("narrow_group", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("bucket_da", ctypes.c_double)]
+
+
+_sig("homs_batched_config_get", [_P, ctypes.POINTER(_BatchedConfig)])
+_sig("homs_batched_config_set", [_P, ctypes.POINTER(_BatchedConfig)])
+_sig("homs_search_batched", [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _i32, _P])
+_sig("homs_autotune_batched", [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _i32,
+                               ctypes.POINTER(_BatchedConfig), ctypes.POINTER(ctypes.c_double),
+                               _P])
+
 EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_last_error",
             "homs_preprocess", "homs_create", "homs_destroy", "homs_generate_codebook", "homs_set_codebook",
             "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
             "homs_library_size", "homs_library_export", "homs_window_bounds",
             "homs_search_window", "homs_debug_distances", "homs_device_errors",
-            "homs_profile_enable", "homs_profile_read"]
+            "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
+            "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched"]
 
 
 @dataclass(frozen=True)
@@ -358,6 +373,56 @@ class Context:
             _dptr(idx, torch.int64, "idx", self.device),
             _dptr(dist, torch.int32, "dist", self.device), _stream(self.device)))
         return row_off, idx[:tot], dist[:tot]
+
+    # --- batched (mixed-window) search
+    def batched_config(self) -> dict:
+        c = _BatchedConfig()
+        self._ck(_lib.homs_batched_config_get(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in _BatchedConfig._fields_}
+
+    def set_batched_config(self, **kw):
+        cfg = self.batched_config()
+        cfg.update(kw)
+        c = _BatchedConfig(**cfg)
+        self._ck(_lib.homs_batched_config_set(self._h, ctypes.byref(c)))
+
+    def _batched_args(self, q_hv, pmz, charge, kinds, values, out_idx, out_dist):
+        import torch
+        nq = pmz.shape[0]
+        if q_hv.shape != (nq, self.words):
+            raise ValueError("q_hv must be [nq, D/32]")
+        if out_idx is None:
+            out_idx = torch.empty(nq, dtype=torch.int64, device=self.device)
+        if out_dist is None:
+            out_dist = torch.empty(nq, dtype=torch.int32, device=self.device)
+        args = (nq, _dptr(q_hv, torch.int32, "q_hv", self.device),
+                _dptr(pmz, torch.float64, "pmz", self.device),
+                _dptr(charge, torch.int8, "charge", self.device),
+                _dptr(kinds, torch.int8, "kinds", self.device),
+                _dptr(values, torch.float64, "values", self.device),
+                _dptr(out_idx, torch.int64, "out_idx", self.device),
+                _dptr(out_dist, torch.int32, "out_dist", self.device))
+        return args, out_idx, out_dist
+
+    def search_batched(self, q_hv, pmz, charge, kinds, values, use_graph=True, out_idx=None,
+                       out_dist=None):
+        """homs_search_batched: per-query windows (kinds: 0 Da / 1 ppm) in one launch."""
+        args, out_idx, out_dist = self._batched_args(q_hv, pmz, charge, kinds, values, out_idx,
+                                                     out_dist)
+        self._ck(_lib.homs_search_batched(self._h, *args, int(bool(use_graph)),
+                                          _stream(self.device)))
+        return out_idx, out_dist
+
+    def autotune_batched(self, q_hv, pmz, charge, kinds, values, reps=2, out_idx=None,
+                         out_dist=None):
+        """homs_autotune_batched -> (best config dict, ms per batch)."""
+        args, out_idx, out_dist = self._batched_args(q_hv, pmz, charge, kinds, values, out_idx,
+                                                     out_dist)
+        best = _BatchedConfig()
+        ms = ctypes.c_double(0.0)
+        self._ck(_lib.homs_autotune_batched(self._h, *args, reps, ctypes.byref(best),
+                                            ctypes.byref(ms), _stream(self.device)))
+        return {f: getattr(best, f) for f, _ in _BatchedConfig._fields_}, ms.value
 
     def profile_enable(self, on: bool = True):
         self._ck(_lib.homs_profile_enable(self._h, int(on)))

@@ -96,27 +96,37 @@ def test_every_distance(tiny):
         assert np.array_equal(dist[a:b][order], o_dist[a:b])
 
 
+ENGINES = [0, 1, 2]  # popcount, MFMA int8, MFMA fp8
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("kind,value", [(0, 500.0), (1, 20.0), (0, 0.0), (0, 5.0)])
-def test_top1(tiny, kind, value):
+def test_top1(tiny, kind, value, engine):
     g = tiny.g
-    idx, dist = tiny.ctx.search_window(tiny.q_hv, tiny.q_pmz, tiny.q_ch, kind=kind, value=value)
+    idx, dist = tiny.ctx.search_window(tiny.q_hv, tiny.q_pmz, tiny.q_ch, kind=kind, value=value,
+                                      engine=engine)
     o_idx, o_dist = oracle.search(tiny.op, tiny.o_lib, g.library.pmz, g.library.charge,
                                   tiny.o_q, g.queries.pmz, g.queries.charge, kind, value)
     assert np.array_equal(idx.cpu().numpy(), o_idx)
     assert np.array_equal(dist.cpu().numpy(), o_dist)
 
 
-def test_top1_d8192_ragged():
-    """D = 8192 (Section 4.2) with a query count that leaves a ragged tile."""
-    s = Setup(dim=8192, n_ref=1500, n_query=333, seed=3)
+@pytest.mark.parametrize("dim,n_ref,n_query", [(8192, 1500, 333), (512, 700, 1000),
+                                              (1536, 3000, 257)])
+def test_top1_other_dims_ragged(dim, n_ref, n_query):
+    """D = 8192 (Section 4.2) and other supported D, with query counts that
+    leave ragged tiles and library sizes that leave ragged row blocks; every
+    engine must agree with the oracle."""
+    s = Setup(dim=dim, n_ref=n_ref, n_query=n_query, seed=3)
     g = s.g
     try:
         assert np.array_equal(_np_u32(s.q_hv), s.o_q)
-        idx, dist = s.ctx.search_window(s.q_hv, s.q_pmz, s.q_ch)
         o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
                                       g.queries.pmz, g.queries.charge)
-        assert np.array_equal(idx.cpu().numpy(), o_idx)
-        assert np.array_equal(dist.cpu().numpy(), o_dist)
+        for engine in ENGINES:
+            idx, dist = s.ctx.search_window(s.q_hv, s.q_pmz, s.q_ch, engine=engine)
+            assert np.array_equal(idx.cpu().numpy(), o_idx), engine
+            assert np.array_equal(dist.cpu().numpy(), o_dist), engine
     finally:
         s.ctx.close()
 
@@ -130,8 +140,11 @@ def test_exact_copies_and_duplicates(tiny):
     q = subset(g.library, rows)
     qo, qb, ql = h.preprocess(tiny.hp, q.offsets, q.mz, q.intensity)
     qhv = tiny.ctx.encode_queries(*h.to_device_csr(qo, qb, ql, "cuda:0"))
-    idx, dist = tiny.ctx.search_window(qhv, _dev(q.pmz), _dev(q.charge))
     o_q = tiny.o_lib[rows]
+    for engine in ENGINES[1:]:
+        i2, d2 = tiny.ctx.search_window(qhv, _dev(q.pmz), _dev(q.charge), engine=engine)
+        assert np.all(d2.cpu().numpy() == 0)
+    idx, dist = tiny.ctx.search_window(qhv, _dev(q.pmz), _dev(q.charge))
     o_idx, o_dist = oracle.search(tiny.op, tiny.o_lib, g.library.pmz, g.library.charge, o_q,
                                   q.pmz, q.charge)
     assert np.array_equal(idx.cpu().numpy(), o_idx)
@@ -145,10 +158,11 @@ def test_edge_cases(tiny):
     qhv = tiny.q_hv[:4].contiguous()
     pmz = _dev(np.array([np.nan, 900.0, 5000.0, 900.0]))
     ch = _dev(np.array([2, 9, 2, 3], dtype=np.int8))
-    idx, dist = tiny.ctx.search_window(qhv, pmz, ch)
-    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
-    assert idx[:3].tolist() == [-1, -1, -1] and dist[:3].tolist() == [-1, -1, -1]
-    assert idx[3] >= 0
+    for engine in ENGINES:
+        idx, dist = tiny.ctx.search_window(qhv, pmz, ch, engine=engine)
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        assert idx[:3].tolist() == [-1, -1, -1] and dist[:3].tolist() == [-1, -1, -1]
+        assert idx[3] >= 0
     e_idx, e_dist = tiny.ctx.search_window(qhv[:0], pmz[:0], ch[:0])
     assert e_idx.numel() == 0 and e_dist.numel() == 0
     torch.cuda.synchronize()
@@ -178,7 +192,6 @@ def test_custom_codebook_ties(distinct):
         ctx.encode_library(*h.to_device_csr(lo, lb, ll, "cuda:0"), _dev(g.library.pmz),
                            _dev(g.library.charge))
         qhv = ctx.encode_queries(*h.to_device_csr(qo, qb, ql, "cuda:0"))
-        idx, dist = ctx.search_window(qhv, _dev(g.queries.pmz), _dev(g.queries.charge))
         o_lib = oracle.encode(op, idt, lvt, lo, lb, ll)
         o_q = oracle.encode(op, idt, lvt, qo, qb, ql)
         assert np.array_equal(_np_u32(qhv), o_q)
@@ -186,8 +199,11 @@ def test_custom_codebook_ties(distinct):
                                       g.queries.pmz, g.queries.charge)
         # the codebook makes many library vectors identical: ties are real
         assert len(np.unique(o_lib, axis=0)) < len(o_lib)
-        assert np.array_equal(idx.cpu().numpy(), o_idx)
-        assert np.array_equal(dist.cpu().numpy(), o_dist)
+        for engine in ENGINES:
+            idx, dist = ctx.search_window(qhv, _dev(g.queries.pmz), _dev(g.queries.charge),
+                                          engine=engine)
+            assert np.array_equal(idx.cpu().numpy(), o_idx), engine
+            assert np.array_equal(dist.cpu().numpy(), o_dist), engine
 
 
 def test_encode_range_error_flag():
