@@ -1,0 +1,133 @@
+"""Learned-shortlist oracle — TEST INFRASTRUCTURE ONLY.
+
+Float64 numpy definition of the small MLP that embeds hypervectors for the
+learned shortlist (not in the paper; the paper's search is the exhaustive
+Hamming top-1 of Section 3.4, which stays the judge):
+
+    x  = bipolar form of the packed hypervector (bit 0 -> +1, bit 1 -> -1)
+    a1 = W1 x + b1,   h = ReLU(a1)                      (D -> H)
+    z  = W2 h + b2                                      (H -> E)
+    e  = z / sqrt(z.z + eps)                            (unit embedding)
+    score(q, r) = e_q . e_r
+
+Training loss for a batch of B (query, exact top-1 reference) pairs is
+InfoNCE with in-batch negatives and temperature tau:
+
+    S_ij = e_qi . e_rj / tau,   loss = mean_i [logsumexp_j S_ij - S_ii]
+
+Adam (Kingma & Ba, 2015) updates the weights. The shortlist of a query is
+the k candidates of its window (Section 3.4) with the largest scores, ties to
+the lower library index; the answer is the exhaustive top-1 restricted to the
+shortlist. Only tests, the smoke check and the benchmark's CPU baseline may
+import this module; it imports nothing from the product package.
+"""
+from __future__ import annotations
+
+from typing import Dict, Tuple
+
+import numpy as np
+
+EPS_NORM = 1e-12
+
+
+def bipolar(hv: np.ndarray, dim: int) -> np.ndarray:
+    """Packed uint32 rows [n, D/32] -> float64 +-1 [n, D]."""
+    bits = np.unpackbits(np.ascontiguousarray(hv, dtype=np.uint32).view(np.uint8), axis=1,
+                         bitorder="little")[:, :dim]
+    return 1.0 - 2.0 * bits.astype(np.float64)
+
+
+def init_params(dim: int, hidden: int, embed: int, rng: np.random.Generator
+                ) -> Dict[str, np.ndarray]:
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases (drawn by
+    the caller's generator and handed to both sides)."""
+    return {
+        "W1": rng.uniform(-1, 1, (hidden, dim)) / np.sqrt(dim),
+        "b1": np.zeros(hidden),
+        "W2": rng.uniform(-1, 1, (embed, hidden)) / np.sqrt(hidden),
+        "b2": np.zeros(embed),
+    }
+
+
+def forward(p: Dict[str, np.ndarray], X: np.ndarray) -> Dict[str, np.ndarray]:
+    a1 = X @ p["W1"].T + p["b1"]
+    h = np.maximum(a1, 0.0)
+    z = h @ p["W2"].T + p["b2"]
+    s = np.sqrt((z * z).sum(axis=1, keepdims=True) + EPS_NORM)
+    return {"X": X, "a1": a1, "h": h, "z": z, "s": s, "e": z / s}
+
+
+def embed(p, X):
+    return forward(p, X)["e"]
+
+
+def info_nce(Eq: np.ndarray, Er: np.ndarray, tau: float) -> Tuple[float, np.ndarray, np.ndarray]:
+    """Loss and its gradients with respect to the query and reference embeddings."""
+    B = Eq.shape[0]
+    S = Eq @ Er.T / tau
+    m = S.max(axis=1, keepdims=True)
+    P = np.exp(S - m)
+    Z = P.sum(axis=1, keepdims=True)
+    loss = float(np.mean(np.log(Z[:, 0]) + m[:, 0] - np.diag(S)))
+    dS = (P / Z - np.eye(B)) / B
+    return loss, dS @ Er / tau, dS.T @ Eq / tau
+
+
+def backward(p, c, dE) -> Dict[str, np.ndarray]:
+    e, s = c["e"], c["s"]
+    dz = (dE - e * (e * dE).sum(axis=1, keepdims=True)) / s
+    g = {"W2": dz.T @ c["h"], "b2": dz.sum(axis=0)}
+    dh = dz @ p["W2"]
+    da1 = dh * (c["a1"] > 0.0)
+    g["W1"] = da1.T @ c["X"]
+    g["b1"] = da1.sum(axis=0)
+    return g
+
+
+def loss_and_grads(p, Xq: np.ndarray, Xr: np.ndarray, tau: float):
+    """Loss of a batch of pairs and the gradient of every parameter (the
+    query and reference towers share the weights, so gradients add)."""
+    cq, cr = forward(p, Xq), forward(p, Xr)
+    loss, dEq, dEr = info_nce(cq["e"], cr["e"], tau)
+    gq, gr = backward(p, cq, dEq), backward(p, cr, dEr)
+    return loss, {k: gq[k] + gr[k] for k in gq}
+
+
+def adam(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place; state holds m, v per parameter and the step t."""
+    t = state.get("t", 0) + 1
+    state["t"] = t
+    for k in p:
+        m = state.setdefault("m_" + k, np.zeros_like(p[k]))
+        v = state.setdefault("v_" + k, np.zeros_like(p[k]))
+        m[...] = beta1 * m + (1 - beta1) * g[k]
+        v[...] = beta2 * v + (1 - beta2) * g[k] * g[k]
+        mh = m / (1 - beta1 ** t)
+        vh = v / (1 - beta2 ** t)
+        p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+    return p
+
+
+def shortlist_search(E_lib, E_q, lib_hv, q_hv, lib_pmz, lib_charge, q_pmz, q_charge, k,
+                     tol_da=500.0, dim=8192):
+    """Top-k candidates by embedding score within each query's window (ties to
+    the lower library index), then the exact Hamming top-1 over them.
+    Returns (index, distance, shortlist) per query; (-1, -1) without candidates."""
+    nq = E_q.shape[0]
+    idx = np.full(nq, -1, dtype=np.int64)
+    dist = np.full(nq, -1, dtype=np.int32)
+    lists = []
+    for i in range(nq):
+        lo, hi = q_pmz[i] - tol_da, q_pmz[i] + tol_da
+        cand = np.flatnonzero((lib_charge == q_charge[i]) & (lib_pmz >= lo) & (lib_pmz <= hi))
+        if cand.size == 0:
+            lists.append(cand)
+            continue
+        sc = E_lib[cand] @ E_q[i]
+        order = np.lexsort((cand, -sc))[:k]
+        short = cand[order]
+        lists.append(short)
+        h = np.bitwise_count(lib_hv[short] ^ q_hv[i]).sum(axis=1)
+        j = np.lexsort((short, h))[0]
+        idx[i], dist[i] = short[j], h[j]
+    return idx, dist, lists

@@ -1,0 +1,109 @@
+"""Pins of the learned-shortlist oracle: analytic gradients against central
+finite differences in float64, closed forms of the loss and of the unit
+embedding, the Adam update against its first-step closed form, and the
+shortlist search against brute force."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _small(seed=0, D=64, H=16, E=8, B=5):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(D, H, E, rng)
+    p["b1"] = rng.normal(0, 0.1, H)
+    p["b2"] = rng.normal(0, 0.1, E)
+    Xq = np.where(rng.random((B, D)) < 0.5, 1.0, -1.0)
+    Xr = np.where(rng.random((B, D)) < 0.5, 1.0, -1.0)
+    return p, Xq, Xr
+
+
+def test_gradients_match_finite_differences():
+    p, Xq, Xr = _small()
+    tau = 0.1
+    loss, g = mlp.loss_and_grads(p, Xq, Xr, tau)
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2"):
+        flat = p[name].reshape(-1)
+        for j in rng.choice(flat.size, size=min(25, flat.size), replace=False):
+            old = flat[j]
+            flat[j] = old + h
+            lp, _ = mlp.loss_and_grads(p, Xq, Xr, tau)
+            flat[j] = old - h
+            lm, _ = mlp.loss_and_grads(p, Xq, Xr, tau)
+            flat[j] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[j]
+            assert abs(fd - an) <= 1e-6 + 1e-5 * abs(fd), (name, j, fd, an)
+
+
+def test_loss_closed_forms():
+    """Equal embeddings everywhere: every logit is 1/tau, so the loss is
+    log(B); orthonormal query/reference pairs: loss = log(1 + (B-1) e^(-1/tau))."""
+    B, tau = 6, 0.2
+    E = np.tile(np.eye(8)[:1], (B, 1))
+    loss, dq, dr = mlp.info_nce(E, E, tau)
+    assert abs(loss - np.log(B)) < 1e-12
+    E = np.eye(8)[:B]
+    loss, _, _ = mlp.info_nce(E, E, tau)
+    assert abs(loss - np.log(1 + (B - 1) * np.exp(-1 / tau))) < 1e-12
+
+
+def test_embedding_is_unit_and_bipolar_unpacking():
+    p, Xq, _ = _small(D=128)
+    e = mlp.embed(p, Xq)
+    assert np.allclose((e * e).sum(axis=1), 1.0, atol=1e-9)
+    hv = np.array([[0x00000001, 0x80000000, 0, 0]], dtype=np.uint32)
+    x = mlp.bipolar(hv, 128)
+    assert x[0, 0] == -1 and x[0, 1] == 1 and x[0, 63] == -1 and x[0, 62] == 1
+    assert (x == 1).sum() == 126
+
+
+def test_adam_first_step_closed_form():
+    """After one step from zero state, m_hat = g and v_hat = g^2, so each
+    weight moves by -lr * g / (|g| + eps)."""
+    p, Xq, Xr = _small(seed=3)
+    loss, g = mlp.loss_and_grads(p, Xq, Xr, 0.1)
+    before = {k: v.copy() for k, v in p.items()}
+    mlp.adam(p, g, {}, lr=1e-2)
+    for k in p:
+        want = before[k] - 1e-2 * g[k] / (np.abs(g[k]) + 1e-8)
+        assert np.allclose(p[k], want, rtol=0, atol=1e-12)
+
+
+def test_training_lowers_the_loss():
+    p, Xq, Xr = _small(seed=4, D=64, H=32, E=8, B=16)
+    st = {}
+    first, _ = mlp.loss_and_grads(p, Xq, Xr, 0.1)
+    for _ in range(60):
+        _, g = mlp.loss_and_grads(p, Xq, Xr, 0.1)
+        mlp.adam(p, g, st, lr=3e-3)
+    last, _ = mlp.loss_and_grads(p, Xq, Xr, 0.1)
+    assert last < 0.5 * first
+
+
+def test_shortlist_search_brute_force():
+    rng = np.random.default_rng(6)
+    D, nl, nq, k = 128, 80, 12, 5
+    lib = rng.integers(0, 2**32, size=(nl, D // 32), dtype=np.uint32)
+    q = rng.integers(0, 2**32, size=(nq, D // 32), dtype=np.uint32)
+    El = rng.normal(size=(nl, 4))
+    Eq = rng.normal(size=(nq, 4))
+    El[7] = El[3]  # a score tie: the lower index must be kept first
+    lp = rng.uniform(400, 600, nl)
+    lc = rng.integers(2, 4, nl).astype(np.int8)
+    qp = rng.uniform(400, 600, nq)
+    qc = rng.integers(2, 4, nq).astype(np.int8)
+    idx, dist, lists = mlp.shortlist_search(El, Eq, lib, q, lp, lc, qp, qc, k, tol_da=50.0,
+                                            dim=D)
+    for i in range(nq):
+        cand = [r for r in range(nl) if lc[r] == qc[i] and abs(lp[r] - qp[i]) <= 50.0]
+        ranked = sorted(cand, key=lambda r: (-float(El[r] @ Eq[i]), r))[:k]
+        assert list(lists[i]) == ranked
+        if ranked:
+            best = min(ranked, key=lambda r: (sum(bin(int(a) ^ int(b)).count("1")
+                                                  for a, b in zip(lib[r], q[i])), r))
+            assert idx[i] == best
+        else:
+            assert (idx[i], dist[i]) == (-1, -1)
