@@ -306,6 +306,15 @@ typedef struct homs_profile {
 homs_status homs_profile_enable(homs_ctx *ctx, int32_t enable);
 homs_status homs_profile_read(homs_ctx *ctx, homs_profile *out);
 
+/*
+ * Measurement support: sustained rate, in 32-bit lane operations per second,
+ * of the v_xor_b32 + v_bcnt_u32_b32 pair the popcount search is made of,
+ * from a kernel of 16 independent chains per lane filling every compute unit
+ * of `device` (best of three runs). Synchronous; allocates and frees a small
+ * device buffer.
+ */
+homs_status homs_measure_xor_popcount_rate(int32_t device, double *lane_ops_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -122,7 +122,17 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_library_size", "homs_library_export", "homs_window_bounds",
             "homs_search_window", "homs_debug_distances", "homs_device_errors",
             "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
-            "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched"]
+            "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched",
+            "homs_measure_xor_popcount_rate"]
+
+_sig("homs_measure_xor_popcount_rate", [_i32, ctypes.POINTER(ctypes.c_double)])
+
+
+def measure_xor_popcount_rate(device: int = 0) -> float:
+    """homs_measure_xor_popcount_rate: sustained xor+popcount lane-ops/s."""
+    r = ctypes.c_double(0.0)
+    _check(_lib.homs_measure_xor_popcount_rate(device, ctypes.byref(r)))
+    return r.value
 
 
 @dataclass(frozen=True)
