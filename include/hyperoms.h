@@ -307,6 +307,92 @@ homs_status homs_profile_enable(homs_ctx *ctx, int32_t enable);
 homs_status homs_profile_read(homs_ctx *ctx, homs_profile *out);
 
 /*
+ * ---- Learned shortlist ------------------------------------------------------
+ * An extension beyond the paper: a small MLP embeds hypervectors into unit
+ * vectors so that a query's exact nearest reference scores high; the search
+ * then rescores only the k best-scoring candidates of each Section 3.4
+ * window exactly by Hamming distance. The answer is the Section 3.4 top-1
+ * restricted to that shortlist (exact whenever the true nearest candidate is
+ * in it); queries whose shortlist cannot be formed fall back to the
+ * exhaustive window search.
+ *
+ * Network (D -> hidden -> embed): x = bipolar form of the hypervector (bit 0
+ * -> +1, bit 1 -> -1); h = ReLU(W1 x + b1); z = W2 h + b2;
+ * e = z / sqrt(z.z + 1e-12); score(q, r) = e_q . e_r. Weights are fp32 masters
+ * (row-major W1[hidden][D], W2[embed][hidden]) with bf16 copies feeding
+ * matrix-core GEMMs that accumulate in fp32; hidden activations are rounded
+ * to bf16 between the layers.
+ * Training: InfoNCE over a batch of B (query, reference) pairs with in-batch
+ * negatives, S_ij = e_qi . e_rj / tau, loss = mean_i (logsumexp_j S_ij - S_ii),
+ * both towers sharing the weights; Adam (0.9, 0.999, 1e-8) updates them.
+ *
+ * A model belongs to one context, must be destroyed before it, and its calls
+ * must not overlap with other calls on that context. Failures are reported
+ * through homs_last_error(ctx).
+ */
+typedef struct homs_model homs_model;
+
+/* New model on ctx's device with the given initial weights (host fp32:
+ * h_W1[hidden][D], h_b1[hidden], h_W2[embed][hidden], h_b2[embed]); hidden and
+ * embed are multiples of 32 (hidden <= 8192, embed <= 4096). Synchronous. */
+homs_status homs_model_create(homs_ctx *ctx, int32_t hidden, int32_t embed, const float *h_W1,
+                              const float *h_b1, const float *h_W2, const float *h_b2,
+                              homs_model **out);
+void homs_model_destroy(homs_model *model);
+
+/* Replaces the weights and resets the optimiser state. Synchronous. */
+homs_status homs_model_set_weights(homs_model *model, const float *h_W1, const float *h_b1,
+                                   const float *h_W2, const float *h_b2);
+
+/* Copies the fp32 weights to the host (NULL skips an array). Synchronous
+ * (waits for the device). */
+homs_status homs_model_get_weights(homs_model *model, float *h_W1, float *h_b1, float *h_W2,
+                                   float *h_b2);
+
+/* Unit embeddings d_out[n][embed] (fp32) of d_hv[n][D/32]. Asynchronous. */
+homs_status homs_model_embed(homs_model *model, int64_t n, const uint32_t *d_hv, float *d_out,
+                             void *stream);
+
+/* Loss and gradients of one batch without updating the weights: d_q_hv and
+ * d_r_hv hold `batch` rows each (16-byte aligned; batch a multiple of 32 in
+ * [32, 16384]), pair i = (query row i, reference row i). Host outputs with the
+ * weights' shapes (NULL skips one). Synchronous. */
+homs_status homs_model_gradients(homs_model *model, int32_t batch, const uint32_t *d_q_hv,
+                                 const uint32_t *d_r_hv, float tau, float *h_loss, float *h_gW1,
+                                 float *h_gb1, float *h_gW2, float *h_gb2, void *stream);
+
+/* One training step (loss, gradients, Adam update with learning rate lr); the
+ * batch loss is written to d_loss[0] (device float). Asynchronous. */
+homs_status homs_model_train_step(homs_model *model, int32_t batch, const uint32_t *d_q_hv,
+                                  const uint32_t *d_r_hv, float tau, float lr, float *d_loss,
+                                  void *stream);
+
+/* Embeds the context's encoded library (model-owned bf16 rows, sorted
+ * library order). Needed before homs_search_learned and again after the
+ * library or the weights change. Asynchronous; grows its buffer (a device
+ * allocation) when the library grew. */
+homs_status homs_model_embed_library(homs_model *model, void *stream);
+
+/*
+ * Shortlist search: for each query, the k (1 <= k <= 1024) candidates of its
+ * window with the largest scores (ties to the lower library index) are
+ * rescored exactly; d_out_idx / d_out_dist are the Hamming top-1 over them
+ * (lowest library index among equal distances; -1 / -1 without candidates).
+ * d_out_fallback[q] = 1 marks a query whose shortlist could not be formed
+ * (its candidate buffer overflowed or a sampled score threshold kept fewer
+ * than min(k, window) candidates); its result is the exhaustive window
+ * search. d_out_shortlist (optional, [nq][k] int64) receives each query's
+ * shortlist by descending score, -1 past the window's size and for fallback
+ * queries. Same query arguments as homs_search_window. Asynchronous; grows
+ * the context's workspace on first use of a larger nq.
+ */
+homs_status homs_search_learned(homs_ctx *ctx, homs_model *model, int64_t nq,
+                                const uint32_t *d_q_hv, const double *d_q_pmz,
+                                const int8_t *d_q_charge, const homs_window *win, int32_t k,
+                                int64_t *d_out_idx, int32_t *d_out_dist, uint8_t *d_out_fallback,
+                                int64_t *d_out_shortlist, void *stream);
+
+/*
  * Measurement support: sustained rate, in 32-bit lane operations per second,
  * of the v_xor_b32 + v_bcnt_u32_b32 pair the popcount search is made of,
  * from a kernel of 16 independent chains per lane filling every compute unit

@@ -49,16 +49,36 @@ def init_params(dim: int, hidden: int, embed: int, rng: np.random.Generator
     }
 
 
-def forward(p: Dict[str, np.ndarray], X: np.ndarray) -> Dict[str, np.ndarray]:
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Nearest bfloat16 value (ties to even) of each element, as float64: the
+    value is first rounded to float32, then its 32-bit pattern is rounded to
+    the upper 16 bits (finite inputs)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p: Dict[str, np.ndarray], X: np.ndarray, round_hidden: bool = False
+            ) -> Dict[str, np.ndarray]:
+    """round_hidden rounds h to bfloat16, the precision in which the hidden
+    layer is handed to the second layer when the weights are stored in
+    bfloat16 (pass bfloat16-rounded weights alongside)."""
     a1 = X @ p["W1"].T + p["b1"]
     h = np.maximum(a1, 0.0)
+    if round_hidden:
+        h = round_bf16(h)
     z = h @ p["W2"].T + p["b2"]
     s = np.sqrt((z * z).sum(axis=1, keepdims=True) + EPS_NORM)
     return {"X": X, "a1": a1, "h": h, "z": z, "s": s, "e": z / s}
 
 
-def embed(p, X):
-    return forward(p, X)["e"]
+def embed(p, X, round_hidden: bool = False):
+    return forward(p, X, round_hidden)["e"]
+
+
+def rounded_weights(p: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
+    """Weights as stored for bfloat16 matrix products (biases stay exact)."""
+    return {"W1": round_bf16(p["W1"]), "b1": p["b1"], "W2": round_bf16(p["W2"]), "b2": p["b2"]}
 
 
 def info_nce(Eq: np.ndarray, Er: np.ndarray, tau: float) -> Tuple[float, np.ndarray, np.ndarray]:
@@ -84,10 +104,10 @@ def backward(p, c, dE) -> Dict[str, np.ndarray]:
     return g
 
 
-def loss_and_grads(p, Xq: np.ndarray, Xr: np.ndarray, tau: float):
+def loss_and_grads(p, Xq: np.ndarray, Xr: np.ndarray, tau: float, round_hidden: bool = False):
     """Loss of a batch of pairs and the gradient of every parameter (the
     query and reference towers share the weights, so gradients add)."""
-    cq, cr = forward(p, Xq), forward(p, Xr)
+    cq, cr = forward(p, Xq, round_hidden), forward(p, Xr, round_hidden)
     loss, dEq, dEr = info_nce(cq["e"], cr["e"], tau)
     gq, gr = backward(p, cq, dEq), backward(p, cr, dEr)
     return loss, {k: gq[k] + gr[k] for k in gq}

@@ -10,6 +10,7 @@
 
 #include "codebook.h"
 #include "internal.h"
+#include "learned.h"
 #include "preprocess.h"
 
 namespace {
@@ -132,6 +133,7 @@ void free_library(homs::Library& L)
     if (L.pmz) (void)hipFree(L.pmz);
     if (L.charge) (void)hipFree(L.charge);
     if (L.orig) (void)hipFree(L.orig);
+    if (L.slot) (void)hipFree(L.slot);
     L = homs::Library{};
 }
 
@@ -444,6 +446,7 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     free_library(c->lib);
     c->lib_valid = false;
     drop_graph(c);
+    c->lib_gen += 1;
     if (n == 0) {
         c->lib_valid = true;
         return HOMS_OK;
@@ -452,7 +455,6 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     L.n = n;
     const size_t tmp_bytes = homs::library_sort_temp_bytes(n);
     void* tmp = nullptr;
-    uint32_t* slot = nullptr;
     hipError_t e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
     if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
@@ -460,17 +462,16 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     const size_t orig_pad = (size_t)homs::search_mfma_row_pad();
     if (e == hipSuccess) e = hipMalloc(&L.orig, ((size_t)n + orig_pad) * 4);
     if (e == hipSuccess) e = hipMemsetAsync(L.orig + n, 0, orig_pad * 4, s);
-    if (e == hipSuccess) e = hipMalloc(&slot, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc(&L.slot, (size_t)n * 4);
     if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
     if (e == hipSuccess)
         e = homs::launch_library_sort(n, d_pmz, d_charge, c->p.charge_match != 0, tmp, tmp_bytes,
-                                      L.orig, L.pmz, L.charge, slot, s);
-    if (e == hipSuccess) e = homs::launch_encode(c, n, d_offsets, d_bin, d_level, slot, L.hv, s);
+                                      L.orig, L.pmz, L.charge, L.slot, s);
+    if (e == hipSuccess) e = homs::launch_encode(c, n, d_offsets, d_bin, d_level, L.slot, L.hv, s);
     uint32_t flags = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flags, c->d_err, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (slot) (void)hipFree(slot);
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) {
         free_library(L);
@@ -483,6 +484,7 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     }
     c->lib = L;
     c->lib_valid = true;
+    c->lib_gen += 1;
     return HOMS_OK;
 }
 
@@ -885,6 +887,293 @@ homs_status homs_profile_read(homs_ctx* c, homs_profile* out)
         c->prof.ms[k] = 0;
         c->prof.launches[k] = 0;
     }
+    return HOMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned shortlist
+
+namespace {
+
+homs_status model_usable(homs_model* m)
+{
+    if (!m) return fail(nullptr, HOMS_E_INVALID, "model is NULL");
+    if (homs_status s = usable(m->ctx)) return s;
+    return HOMS_OK;
+}
+
+homs_status model_copy_weights(homs_model* m, const float* W1, const float* b1, const float* W2,
+                               const float* b2)
+{
+    homs_ctx* c = m->ctx;
+    const size_t n1 = (size_t)m->H * m->D, n2 = (size_t)m->E * m->H;
+    HIP_TRY(c, hipMemcpy(m->W1, W1, n1 * 4, hipMemcpyHostToDevice), "hipMemcpy(W1)");
+    HIP_TRY(c, hipMemcpy(m->b1, b1, (size_t)m->H * 4, hipMemcpyHostToDevice), "hipMemcpy(b1)");
+    HIP_TRY(c, hipMemcpy(m->W2, W2, n2 * 4, hipMemcpyHostToDevice), "hipMemcpy(W2)");
+    HIP_TRY(c, hipMemcpy(m->b2, b2, (size_t)m->E * 4, hipMemcpyHostToDevice), "hipMemcpy(b2)");
+    for (void* p : {(void*)m->mW1, (void*)m->vW1, (void*)m->mW2, (void*)m->vW2})
+        HIP_TRY(c, hipMemset(p, 0, (p == m->mW1 || p == m->vW1 ? n1 : n2) * 4), "hipMemset");
+    HIP_TRY(c, hipMemset(m->mb1, 0, (size_t)m->H * 4), "hipMemset");
+    HIP_TRY(c, hipMemset(m->vb1, 0, (size_t)m->H * 4), "hipMemset");
+    HIP_TRY(c, hipMemset(m->mb2, 0, (size_t)m->E * 4), "hipMemset");
+    HIP_TRY(c, hipMemset(m->vb2, 0, (size_t)m->E * 4), "hipMemset");
+    HIP_TRY(c, homs::model_refresh_bf16(m, nullptr), "weight conversion kernels");
+    HIP_TRY(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    m->step = 0;
+    m->weights_gen += 1;
+    return HOMS_OK;
+}
+
+bool pairs_valid(int32_t batch, const uint32_t* q, const uint32_t* r, std::string* why)
+{
+    if (batch < 32 || batch > 16384 || batch % 32 != 0) {
+        *why = "batch must be a multiple of 32 in [32, 16384]";
+        return false;
+    }
+    if (!q || !r || !aligned16(q) || !aligned16(r)) {
+        *why = "pair rows must be non-NULL and 16-byte aligned";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+homs_status homs_model_create(homs_ctx* c, int32_t hidden, int32_t embed, const float* h_W1,
+                              const float* h_b1, const float* h_W2, const float* h_b2,
+                              homs_model** out)
+{
+    if (!out) return fail(nullptr, HOMS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (homs_status s = usable(c)) return s;
+    if (hidden < 32 || hidden > 8192 || hidden % 32 != 0 || embed < 32 || embed > 4096 ||
+        embed % 32 != 0)
+        return fail(c, HOMS_E_INVALID, "hidden and embed must be multiples of 32 (hidden <= 8192, "
+                                       "embed <= 4096)");
+    if (!h_W1 || !h_b1 || !h_W2 || !h_b2) return fail(c, HOMS_E_INVALID, "NULL weight array");
+    DeviceGuard g(c->device);
+    homs_model* m = new (std::nothrow) homs_model();
+    if (!m) return fail(c, HOMS_E_OOM, "host allocation failed");
+    m->ctx = c;
+    m->D = (int)c->p.dim;
+    m->H = hidden;
+    m->E = embed;
+    hipError_t e = homs::model_alloc(m);
+    if (e != hipSuccess) {
+        homs::model_free(m);
+        delete m;
+        return hip_fail(c, e, "model allocation");
+    }
+    if (homs_status s = model_copy_weights(m, h_W1, h_b1, h_W2, h_b2)) {
+        homs::model_free(m);
+        delete m;
+        return s;
+    }
+    *out = m;
+    return HOMS_OK;
+}
+
+void homs_model_destroy(homs_model* m)
+{
+    if (!m) return;
+    DeviceGuard g(m->ctx->device);
+    (void)hipDeviceSynchronize();
+    homs::model_free(m);
+    delete m;
+}
+
+homs_status homs_model_set_weights(homs_model* m, const float* h_W1, const float* h_b1,
+                                   const float* h_W2, const float* h_b2)
+{
+    if (homs_status s = model_usable(m)) return s;
+    if (!h_W1 || !h_b1 || !h_W2 || !h_b2) return fail(m->ctx, HOMS_E_INVALID, "NULL weight array");
+    DeviceGuard g(m->ctx->device);
+    return model_copy_weights(m, h_W1, h_b1, h_W2, h_b2);
+}
+
+homs_status homs_model_get_weights(homs_model* m, float* h_W1, float* h_b1, float* h_W2,
+                                   float* h_b2)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const size_t n1 = (size_t)m->H * m->D, n2 = (size_t)m->E * m->H;
+    if (h_W1) HIP_TRY(c, hipMemcpy(h_W1, m->W1, n1 * 4, hipMemcpyDeviceToHost), "hipMemcpy(W1)");
+    if (h_b1)
+        HIP_TRY(c, hipMemcpy(h_b1, m->b1, (size_t)m->H * 4, hipMemcpyDeviceToHost), "hipMemcpy(b1)");
+    if (h_W2) HIP_TRY(c, hipMemcpy(h_W2, m->W2, n2 * 4, hipMemcpyDeviceToHost), "hipMemcpy(W2)");
+    if (h_b2)
+        HIP_TRY(c, hipMemcpy(h_b2, m->b2, (size_t)m->E * 4, hipMemcpyDeviceToHost), "hipMemcpy(b2)");
+    return HOMS_OK;
+}
+
+homs_status homs_model_embed(homs_model* m, int64_t n, const uint32_t* d_hv, float* d_out,
+                             void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "n out of range");
+    if (n == 0) return HOMS_OK;
+    if (!d_hv || !d_out) return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, homs::model_embed(m, n, d_hv, d_out, nullptr, (hipStream_t)stream),
+            "embedding kernels");
+    return HOMS_OK;
+}
+
+homs_status homs_model_gradients(homs_model* m, int32_t batch, const uint32_t* d_q_hv,
+                                 const uint32_t* d_r_hv, float tau, float* h_loss, float* h_gW1,
+                                 float* h_gb1, float* h_gW2, float* h_gb2, void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    std::string why;
+    if (!pairs_valid(batch, d_q_hv, d_r_hv, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!(tau > 0.f) || !std::isfinite(tau)) return fail(c, HOMS_E_INVALID, "tau must be > 0");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    float* d_loss = nullptr;
+    HIP_TRY(c, hipMalloc(&d_loss, 256), "hipMalloc(loss)");
+    hipError_t e = homs::model_step(m, batch, d_q_hv, d_r_hv, tau, 0.f, false, d_loss, s);
+    float loss = 0.f;
+    if (e == hipSuccess) e = hipMemcpyAsync(&loss, d_loss, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_loss);
+    if (e != hipSuccess) return hip_fail(c, e, "training kernels");
+    const size_t n1 = (size_t)m->H * m->D, n2 = (size_t)m->E * m->H;
+    if (h_loss) *h_loss = loss;
+    if (h_gW1) HIP_TRY(c, hipMemcpy(h_gW1, m->gW1, n1 * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (h_gb1) HIP_TRY(c, hipMemcpy(h_gb1, m->gb1, (size_t)m->H * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (h_gW2) HIP_TRY(c, hipMemcpy(h_gW2, m->gW2, n2 * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (h_gb2) HIP_TRY(c, hipMemcpy(h_gb2, m->gb2, (size_t)m->E * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    return HOMS_OK;
+}
+
+homs_status homs_model_train_step(homs_model* m, int32_t batch, const uint32_t* d_q_hv,
+                                  const uint32_t* d_r_hv, float tau, float lr, float* d_loss,
+                                  void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    std::string why;
+    if (!pairs_valid(batch, d_q_hv, d_r_hv, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!(tau > 0.f) || !std::isfinite(tau)) return fail(c, HOMS_E_INVALID, "tau must be > 0");
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(c, HOMS_E_INVALID, "lr must be >= 0");
+    if (!d_loss) return fail(c, HOMS_E_INVALID, "d_loss is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, homs::model_step(m, batch, d_q_hv, d_r_hv, tau, lr, true, d_loss,
+                                (hipStream_t)stream),
+            "training kernels");
+    m->weights_gen += 1;
+    return HOMS_OK;
+}
+
+homs_status homs_model_embed_library(homs_model* m, void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->lib.n;
+    m->lib_emb_valid = false;
+    if (m->lib_emb_n < n) {
+        HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (m->lib_emb) (void)hipFree(m->lib_emb);
+        m->lib_emb = nullptr;
+        m->lib_emb_n = 0;
+        HIP_TRY(c, hipMalloc(&m->lib_emb, (size_t)std::max<int64_t>(n, 1) * m->E * 2),
+                "hipMalloc(library embeddings)");
+        m->lib_emb_n = n;
+    }
+    if (n > 0)
+        HIP_TRY(c, homs::model_embed(m, n, c->lib.hv, nullptr, m->lib_emb, s), "embedding kernels");
+    m->lib_emb_lib_gen = c->lib_gen;
+    m->lib_emb_w_gen = m->weights_gen;
+    m->lib_emb_valid = true;
+    return HOMS_OK;
+}
+
+homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const uint32_t* d_q_hv,
+                                const double* d_q_pmz, const int8_t* d_q_charge,
+                                const homs_window* win, int32_t k, int64_t* d_out_idx,
+                                int32_t* d_out_dist, uint8_t* d_out_fallback,
+                                int64_t* d_out_shortlist, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!m || m->ctx != c) return fail(c, HOMS_E_INVALID, "model is NULL or of another context");
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (!m->lib_emb_valid || m->lib_emb_lib_gen != c->lib_gen || m->lib_emb_w_gen != m->weights_gen)
+        return fail(c, HOMS_E_STATE, "library embeddings are missing or stale "
+                                     "(call homs_model_embed_library)");
+    if (k < 1 || k > homs::learned_max_k())
+        return fail(c, HOMS_E_INVALID,
+                    "k must be in [1, " + std::to_string(homs::learned_max_k()) + "]");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist || !d_out_fallback)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int tile = homs::search_popcount_tile();
+    homs::LearnedScratchPlan plan;
+    const size_t base = search_scratch_bytes(nq, tile);
+    const size_t extra = 2 * al(nq * 8) + al(nq * (size_t)m->E * 2) +
+                         (d_out_shortlist ? 0 : al(nq * (size_t)k * 8)) +
+                         homs::learned_scratch_bytes(nq, m->E, &plan);
+    if (homs_status st = ensure_workspace(c, base + extra, s)) return st;
+    SearchScratch w = carve(c->ws.ptr, nq, tile);
+    char* p = (char*)c->ws.ptr + base;
+    int64_t* lo2 = (int64_t*)p;
+    p += al(nq * 8);
+    int64_t* hi2 = (int64_t*)p;
+    p += al(nq * 8);
+    uint16_t* q_emb = (uint16_t*)p;
+    p += al(nq * (size_t)m->E * 2);
+    int64_t* shortlist = d_out_shortlist;
+    if (!shortlist) {
+        shortlist = (int64_t*)p;
+        p += al(nq * (size_t)k * 8);
+    }
+    void* lscratch = p;
+
+    hipEvent_t e0 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_window_bounds(c, nq, d_q_pmz, d_q_charge, win->kind, win->value,
+                                          nullptr, nullptr, w.lo, w.hi, s),
+            "window kernel");
+    uint32_t* qperm = nullptr;
+    HIP_TRY(c, homs::launch_query_sort(nq, d_q_pmz, d_q_charge, c->p.charge_match != 0, w.sort_tmp,
+                                       w.sort_bytes, w.qk_a, w.qk_b, w.qp_a, w.qp_b, &qperm, s),
+            "query sort");
+    HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
+    HIP_TRY(c, homs::model_embed(m, nq, d_q_hv, nullptr, q_emb, s), "embedding kernels");
+    hipEvent_t e1 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_search_learned(c, m, lscratch, plan, nq, d_q_hv, q_emb, qperm, w.lo,
+                                           w.hi, k, w.keys, d_out_fallback, shortlist, s),
+            "shortlist kernels");
+    // exhaustive pass over the windows of the queries that fell back
+    HIP_TRY(c, homs::launch_fallback_windows(nq, d_out_fallback, w.lo, w.hi, lo2, hi2, s),
+            "fallback windows kernel");
+    HIP_TRY(c, homs::launch_tile_bounds(nq, qperm, lo2, hi2, tile, w.tile_lo, w.tile_hi, s),
+            "tile bounds kernel");
+    homs::TilePlan tplan;
+    HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, lo2, hi2, w.tile_lo, w.tile_hi,
+                                            tplan, w.keys, s),
+            "fallback search kernel");
+    hipEvent_t e2 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");
+    hipEvent_t e3 = prof_mark(c, s);
+    prof_span(c, e0, e1, homs::kProfPrep);
+    prof_span(c, e1, e2, homs::kProfSearch);
+    prof_span(c, e2, e3, homs::kProfPrep);
     return HOMS_OK;
 }
 

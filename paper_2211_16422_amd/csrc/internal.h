@@ -21,6 +21,7 @@ struct Library {
     double* pmz = nullptr;       // [n] sorted precursor m/z
     int8_t* charge = nullptr;    // [n] sorted charge (all 0 when charge is ignored)
     uint32_t* orig = nullptr;    // [n] library index of each sorted row
+    uint32_t* slot = nullptr;    // [n] sorted row of each library index
 };
 
 struct Workspace {
@@ -70,6 +71,7 @@ struct homs_ctx {
     uint32_t* d_err = nullptr;    // device error flags
     homs::Library lib;
     bool lib_valid = false;
+    uint64_t lib_gen = 0;  // bumped by every homs_encode_library
     homs::Workspace ws;
     homs::Profiler prof;
     homs::BatchedConfig batched;

@@ -1,0 +1,64 @@
+// Internal declarations of the learned shortlist (model state, training and
+// embedding steps, shortlist search). Not part of the C ABI.
+#pragma once
+
+#include <string>
+
+#include "internal.h"
+
+struct homs_model {
+    homs_ctx* ctx = nullptr;
+    int D = 0, H = 0, E = 0;
+    // fp32 masters, Adam moments, bf16 copies (W2 also transposed), gradients
+    float *W1 = nullptr, *b1 = nullptr, *W2 = nullptr, *b2 = nullptr;
+    float *mW1 = nullptr, *vW1 = nullptr, *mb1 = nullptr, *vb1 = nullptr;
+    float *mW2 = nullptr, *vW2 = nullptr, *mb2 = nullptr, *vb2 = nullptr;
+    uint16_t *W1h = nullptr, *W2h = nullptr, *W2Th = nullptr;
+    float *gW1 = nullptr, *gb1 = nullptr, *gW2 = nullptr, *gb2 = nullptr;
+    int64_t step = 0;
+    uint64_t weights_gen = 0;  // bumped by every weight change
+    void* train_ws = nullptr;
+    size_t train_ws_bytes = 0;
+    void* emb_ws = nullptr;
+    size_t emb_ws_bytes = 0;
+    // embeddings of the context's library in sorted order, bf16 [n][E]
+    uint16_t* lib_emb = nullptr;
+    int64_t lib_emb_n = 0;
+    uint64_t lib_emb_lib_gen = 0;  // ctx->lib_gen and weights_gen the embeddings
+    uint64_t lib_emb_w_gen = 0;    // were made from (stale when either moved on)
+    bool lib_emb_valid = false;
+};
+
+namespace homs {
+
+constexpr int64_t kEmbedBatch = 16384;  // rows expanded to bf16 per embedding pass
+
+void model_free(homs_model* m);
+hipError_t model_alloc(homs_model* m);
+hipError_t model_refresh_bf16(homs_model* m, hipStream_t s);
+hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_f32,
+                       uint16_t* out_bf16, hipStream_t s);
+hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t* r_hv, float tau,
+                      float lr, bool update, float* loss, hipStream_t s);
+
+// learned_search.hip: shortlist of k per query, exact rescoring; sets
+// fallback[q] = 1 where the shortlist could not be formed (the caller then
+// runs the exhaustive search for those queries)
+struct LearnedScratchPlan {
+    int64_t batch;  // queries per collection pass
+};
+int learned_max_k();
+size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan);
+hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
+                                 const LearnedScratchPlan& plan, int64_t nq,
+                                 const uint32_t* q_hv, const uint16_t* q_emb,
+                                 const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
+                                 int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
+                                 hipStream_t s);
+// lo2/hi2 = the query's window where fallback[q] is set, else empty
+hipError_t launch_fallback_windows(int64_t nq, const uint8_t* fallback, const int64_t* lo,
+                                   const int64_t* hi, int64_t* lo2, int64_t* hi2, hipStream_t s);
+size_t embed_ws_bytes(const homs_model* m, int64_t rows);
+size_t train_ws_bytes(const homs_model* m, int B);
+
+}  // namespace homs

@@ -1,0 +1,401 @@
+// Shortlist search with the learned embedding.
+//
+// For every query the k candidates of its window (Section 3.4) with the
+// largest embedding scores e_q . e_r are kept (ties to the lower library
+// index) and rescored exactly by Hamming distance; the result is the
+// exhaustive top-1 restricted to that shortlist.
+//
+// Selecting k of up to a few million scores per query is done in one scoring
+// pass over the window:
+//  1. threshold: score a regular sample of the window (every 2^j-th row of
+//     the sorted library, so that neighbouring queries share sample rows in
+//     cache) on the VALU and take the r-th largest sample score, r chosen so
+//     that about min(kTargetMul * k, kCapacity / 2) window candidates are
+//     expected at or above it;
+//     windows of at most kSample candidates keep everything;
+//  2. collect: score every (query, candidate) pair on matrix cores (bf16
+//     operands, fp32 accumulation, 128 library rows x 128 m/z-ordered queries
+//     per workgroup) and append in-window pairs at or above the query's
+//     threshold to its buffer of kCapacity 64-bit keys
+//     (order-preserving score << 32 | ~library index);
+//  3. select: sort each buffer in LDS (bitonic, descending) and keep the k
+//     largest keys; a query whose buffer overflowed, or whose sampled
+//     threshold kept fewer than min(k, window) candidates, is flagged for the
+//     exhaustive fallback and gets no shortlist;
+//  4. rescore: one lane per shortlist entry computes the exact Hamming
+//     distance; the wave minimum of (distance << 32 | library index) is merged
+//     into the query's key.
+#include <algorithm>
+
+#include "gemm_bf16.h"
+#include "learned.h"
+
+namespace homs {
+namespace {
+
+constexpr int kSample = 4096;    // most sampled candidates per window
+constexpr int kTargetMul = 16;   // expected candidates at or above the threshold:
+                                 // min(16 k, kCapacity / 2)
+constexpr int kCapacity = 8192;  // buffer entries per query
+constexpr int kTileQ = 128;      // queries per collection workgroup
+constexpr int64_t kCollectChunk = 4096;  // library rows per collection workgroup
+constexpr int kThreads = 256;
+
+inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads); }
+
+__device__ __forceinline__ float bf(uint32_t v16) { return __uint_as_float(v16 << 16); }
+
+// order-preserving map of a float onto uint32 (larger float, larger key)
+__device__ __forceinline__ uint32_t fkey(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float fkey_inv(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// dst row p = src row perm[p]; 16-byte pieces
+__global__ void permute_rows_kernel(int64_t n, int E, const uint32_t* __restrict__ perm,
+                                    const uint16_t* __restrict__ src, uint16_t* __restrict__ dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = E / 8;
+    if (t >= n * per) return;
+    const int64_t r = t / per;
+    const int c = (int)(t - r * per);
+    ((uint4*)(dst + r * E))[c] = ((const uint4*)(src + (size_t)perm[r] * E))[c];
+}
+
+// Bitonic sort, descending, of n = 2^j keys in LDS by one workgroup.
+__device__ void bitonic_desc(uint64_t* a, int n)
+{
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = (lo & size) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                if (desc ? (x < y) : (x > y)) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// one workgroup per query (sorted position p): its sampled threshold
+__global__ __launch_bounds__(kThreads) void threshold_kernel(
+    int64_t nq, int E, int k, const uint16_t* __restrict__ q_sorted,
+    const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    const int64_t* __restrict__ hi, const uint16_t* __restrict__ lib_emb, float* __restrict__ thr)
+{
+    __shared__ uint64_t s[kSample];
+    const int64_t p = blockIdx.x;
+    const uint32_t qi = qperm[p];
+    const int64_t a = lo[qi], b = hi[qi], w = b - a;
+    if (w <= kSample) {  // the whole window is kept (uniform branch)
+        if (threadIdx.x == 0) thr[p] = -INFINITY;
+        return;
+    }
+    int sh = 1;
+    while (((w + ((int64_t)1 << sh) - 1) >> sh) > kSample) ++sh;
+    const int64_t g0 = (a + ((int64_t)1 << sh) - 1) & ~(((int64_t)1 << sh) - 1);
+    const int ns = (int)((b - g0 + ((int64_t)1 << sh) - 1) >> sh);  // in [kSample/2, kSample]
+    int np = 1;
+    while (np < ns) np <<= 1;
+    const uint16_t* qe = q_sorted + (size_t)p * E;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        uint64_t key = 0;
+        if (i < ns) {
+            const uint16_t* re = lib_emb + (size_t)(g0 + ((int64_t)i << sh)) * E;
+            float acc = 0.f;
+            for (int j = 0; j < E; j += 8) {
+                const uint4 rv = *(const uint4*)(re + j);
+                const uint4 qv = *(const uint4*)(qe + j);
+                acc += bf(rv.x & 0xFFFFu) * bf(qv.x & 0xFFFFu) + bf(rv.x >> 16) * bf(qv.x >> 16);
+                acc += bf(rv.y & 0xFFFFu) * bf(qv.y & 0xFFFFu) + bf(rv.y >> 16) * bf(qv.y >> 16);
+                acc += bf(rv.z & 0xFFFFu) * bf(qv.z & 0xFFFFu) + bf(rv.z >> 16) * bf(qv.z >> 16);
+                acc += bf(rv.w & 0xFFFFu) * bf(qv.w & 0xFFFFu) + bf(rv.w >> 16) * bf(qv.w >> 16);
+            }
+            key = ((uint64_t)fkey(acc) << 32) | (uint32_t)i;
+        }
+        s[i] = key;
+    }
+    __syncthreads();
+    bitonic_desc(s, np);
+    const int64_t target = min((int64_t)kTargetMul * k, (int64_t)kCapacity / 2);
+    int64_t r = (target * ns + w - 1) / w;
+    r = r < 1 ? 1 : (r > ns ? ns : r);
+    if (threadIdx.x == 0) thr[p] = fkey_inv((uint32_t)(s[r - 1] >> 32));
+}
+
+// Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
+// cores and appends every in-window pair at or above the query's threshold.
+__global__ __launch_bounds__(256) void collect_kernel(
+    int E, int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
+    const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    const int64_t* __restrict__ hi, const float* __restrict__ thr,
+    const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
+    const uint16_t* __restrict__ lib_emb, const uint32_t* __restrict__ lib_orig,
+    uint32_t* __restrict__ count, uint64_t* __restrict__ buf)
+{
+    using namespace gemm;
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kTM * kRowBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[2][kTN * kRowBytes];
+    const int64_t tile = blockIdx.x;
+    const int64_t t_hi = tile_hi[tile];
+    const int64_t c0 = tile_lo[tile] + (int64_t)blockIdx.y * kCollectChunk;
+    if (c0 >= t_hi) return;
+    const int64_t c1 = min(c0 + kCollectChunk, t_hi);
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
+    const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
+    const int64_t qlast = q_end - 1;
+
+    // the two query columns each lane owns in the epilogue
+    int64_t qlo[2], qhi[2], qslot[2];
+    float qthr[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t p = p0 + wn * 64 + j * 32 + (l & 31);
+        qslot[j] = p < q_end ? p - q_begin : -1;
+        qlo[j] = qhi[j] = 0;
+        qthr[j] = INFINITY;
+        if (p < q_end) {
+            const uint32_t qi = qperm[p];
+            qlo[j] = lo[qi];
+            qhi[j] = hi[qi];
+            qthr[j] = thr[p];
+        }
+    }
+
+    const int row0 = t >> 1, part0 = (t * 2) & 3;
+    const uint16_t* b_row = q_sorted + (size_t)min(p0 + row0, qlast) * E + part0 * 8;
+    uint8_t* sa_dst = &sA[0][0] + row0 * kRowBytes + part0 * 16;
+    uint8_t* sb_dst = &sB[0][0] + row0 * kRowBytes + part0 * 16;
+    for (int64_t m0 = c0; m0 < c1; m0 += kTM) {
+        const uint16_t* a_row = lib_emb + (size_t)min(m0 + row0, c1 - 1) * E + part0 * 8;
+        Stage st;
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
+        const int nk = E / kTK;
+        st = load_stage(a_row, b_row, 0);
+        store_stage(st, sa_dst, sb_dst, 0);
+        __syncthreads();
+        for (int s = 0; s < nk; ++s) {
+            const int b = s & 1;
+            if (s + 1 < nk) st = load_stage(a_row, b_row, (s + 1) * kTK);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x8 av[2], bv[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    av[i] = *(const bf16x8*)(sA[b] + (wr * 64 + i * 32 + (l & 31)) * kRowBytes +
+                                             ks * 32 + 16 * (l >> 5));
+                    bv[i] = *(const bf16x8*)(sB[b] + (wn * 64 + i * 32 + (l & 31)) * kRowBytes +
+                                             ks * 32 + 16 * (l >> 5));
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j],
+                                                                           acc[i][j], 0, 0, 0);
+            }
+            if (s + 1 < nk) store_stage(st, sa_dst, sb_dst, b ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (qslot[j] < 0) continue;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t g =
+                        m0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                    const float sc = acc[i][j][r];
+                    if (g < c1 && g >= qlo[j] && g < qhi[j] && sc >= qthr[j]) {
+                        const uint32_t slot = atomicAdd(count + qslot[j], 1u);
+                        if (slot < (uint32_t)kCapacity)
+                            buf[(size_t)qslot[j] * kCapacity + slot] =
+                                ((uint64_t)fkey(sc) << 32) | (uint64_t)(0xFFFFFFFFu - lib_orig[g]);
+                    }
+                }
+        }
+    }
+}
+
+// one workgroup per query of the pass: the k largest keys of its buffer
+__global__ __launch_bounds__(kThreads) void select_kernel(
+    int64_t q_begin, int k, const uint32_t* __restrict__ count, const uint64_t* __restrict__ buf,
+    const float* __restrict__ thr, const uint32_t* __restrict__ qperm,
+    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t* __restrict__ shortlist,
+    uint8_t* __restrict__ fallback)
+{
+    extern __shared__ uint64_t sk[];
+    const int64_t p = q_begin + blockIdx.x;
+    const uint32_t qi = qperm[p];
+    const int64_t w = hi[qi] - lo[qi];
+    const uint32_t cnt = count[blockIdx.x];
+    const int n = (int)min(cnt, (uint32_t)kCapacity);
+    const int need = (int)min((int64_t)k, w);
+    const bool sampled = thr[p] != -INFINITY;
+    const bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
+    int np = 1;
+    while (np < n) np <<= 1;
+    if (!bad) {
+        for (int i = threadIdx.x; i < np; i += blockDim.x)
+            sk[i] = i < n ? buf[(size_t)blockIdx.x * kCapacity + i] : 0ull;
+        __syncthreads();
+        if (n > 1) bitonic_desc(sk, np);
+    }
+    int64_t* out = shortlist + (size_t)qi * k;
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        out[i] = (!bad && i < n) ? (int64_t)(0xFFFFFFFFu - (uint32_t)sk[i]) : -1;
+    if (threadIdx.x == 0) fallback[qi] = bad ? 1 : 0;
+}
+
+// one wave per query: exact distances of the shortlist, minimum merged
+__global__ __launch_bounds__(kThreads) void rescore_kernel(
+    int64_t q_begin, int64_t q_end, int k, uint32_t words, const uint32_t* __restrict__ q_hv,
+    const uint32_t* __restrict__ qperm, const int64_t* __restrict__ shortlist,
+    const uint32_t* __restrict__ lib_slot, const uint32_t* __restrict__ lib_hv,
+    uint64_t* __restrict__ keys)
+{
+    const int64_t p = q_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (p >= q_end) return;
+    const uint32_t qi = qperm[p];
+    const uint32_t* qrow = q_hv + (size_t)qi * words;
+    const int64_t* sl = shortlist + (size_t)qi * k;
+    uint64_t best = ~0ull;
+    for (int base = 0; base < k; base += 64) {
+        const int j = base + l;
+        const int64_t o = j < k ? sl[j] : -1;
+        if (o >= 0) {
+            const uint32_t* rp = lib_hv + (size_t)lib_slot[o] * words;
+            uint32_t d = 0;
+            for (uint32_t c = 0; c < words; c += 4) {
+                const uint4 q4 = *(const uint4*)(qrow + c);
+                const uint4 r4 = *(const uint4*)(rp + c);
+                d += __builtin_popcount(q4.x ^ r4.x) + __builtin_popcount(q4.y ^ r4.y) +
+                     __builtin_popcount(q4.z ^ r4.z) + __builtin_popcount(q4.w ^ r4.w);
+            }
+            const uint64_t key = ((uint64_t)d << 32) | (uint64_t)o;
+            best = key < best ? key : best;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t x = __shfl_xor(best, off);
+        best = x < best ? x : best;
+    }
+    if (l == 0 && best != ~0ull)
+        atomicMin((unsigned long long*)(keys + qi), (unsigned long long)best);
+}
+
+// windows of the exhaustive pass: a query's own window if it fell back, else empty
+__global__ void fallback_windows_kernel(int64_t nq, const uint8_t* __restrict__ fallback,
+                                        const int64_t* __restrict__ lo,
+                                        const int64_t* __restrict__ hi, int64_t* __restrict__ lo2,
+                                        int64_t* __restrict__ hi2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    lo2[q] = lo[q];
+    hi2[q] = fallback[q] ? hi[q] : lo[q];
+}
+
+__global__ void zero_u32_kernel(int64_t n, uint32_t* __restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int learned_max_k() { return kCapacity / 8; }
+
+size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
+{
+    LearnedScratchPlan pl;
+    const int64_t budget = (int64_t)1 << 30;  // bytes of candidate buffers per pass
+    pl.batch = std::max<int64_t>(kTileQ, budget / ((int64_t)kCapacity * 8) / kTileQ * kTileQ);
+    pl.batch = std::min<int64_t>(pl.batch, (nq + kTileQ - 1) / kTileQ * kTileQ);
+    pl.batch = std::max<int64_t>(pl.batch, kTileQ);
+    if (plan) *plan = pl;
+    const int64_t tiles = pl.batch / kTileQ;
+    return al(nq * E * 2) + al(nq * 4) + al(pl.batch * 4) + al(pl.batch * (int64_t)kCapacity * 8) +
+           2 * al(tiles * 8);
+}
+
+hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
+                                 const LearnedScratchPlan& plan, int64_t nq,
+                                 const uint32_t* q_hv, const uint16_t* q_emb,
+                                 const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
+                                 int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
+                                 hipStream_t s)
+{
+    if (nq <= 0) return hipSuccess;
+    const int E = m->E;
+    const int64_t tiles_max = plan.batch / kTileQ;
+    char* p = (char*)scratch;
+    uint16_t* q_sorted = (uint16_t*)p;
+    p += al(nq * E * 2);
+    float* thr = (float*)p;
+    p += al(nq * 4);
+    uint32_t* count = (uint32_t*)p;
+    p += al(plan.batch * 4);
+    uint64_t* buf = (uint64_t*)p;
+    p += al(plan.batch * (int64_t)kCapacity * 8);
+    int64_t* tlo = (int64_t*)p;
+    p += al(tiles_max * 8);
+    int64_t* thi = (int64_t*)p;
+
+    permute_rows_kernel<<<blocks_for(nq * (E / 8)), kThreads, 0, s>>>(nq, E, qperm, q_emb,
+                                                                     q_sorted);
+    threshold_kernel<<<(uint32_t)nq, kThreads, 0, s>>>(nq, E, k, q_sorted, qperm, lo, hi,
+                                                       m->lib_emb, thr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
+    if (max_chunks > 65535) return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)kCapacity * 8;
+    for (int64_t b0 = 0; b0 < nq; b0 += plan.batch) {
+        const int64_t b1 = std::min(nq, b0 + plan.batch), nb = b1 - b0;
+        const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
+        e = launch_tile_bounds(nb, qperm + b0, lo, hi, kTileQ, tlo, thi, s);
+        if (e != hipSuccess) return e;
+        zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
+        collect_kernel<<<dim3((uint32_t)tiles, (uint32_t)max_chunks), 256, 0, s>>>(
+            E, b0, b1, q_sorted, qperm, lo, hi, thr, tlo, thi, m->lib_emb, c->lib.orig, count, buf);
+        select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
+                                                          shortlist, fallback);
+        rescore_kernel<<<(uint32_t)((nb + 3) / 4), kThreads, 0, s>>>(
+            b0, b1, k, c->words, q_hv, qperm, shortlist, c->lib.slot, c->lib.hv, keys);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fallback_windows(int64_t nq, const uint8_t* fallback, const int64_t* lo,
+                                   const int64_t* hi, int64_t* lo2, int64_t* hi2, hipStream_t s)
+{
+    if (nq <= 0) return hipSuccess;
+    fallback_windows_kernel<<<blocks_for(nq), kThreads, 0, s>>>(nq, fallback, lo, hi, lo2, hi2);
+    return hipGetLastError();
+}
+
+}  // namespace homs

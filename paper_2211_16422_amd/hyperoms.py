@@ -123,7 +123,22 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_search_window", "homs_debug_distances", "homs_device_errors",
             "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
             "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched",
+            "homs_model_create", "homs_model_destroy", "homs_model_set_weights",
+            "homs_model_get_weights", "homs_model_embed", "homs_model_gradients",
+            "homs_model_train_step", "homs_model_embed_library", "homs_search_learned",
             "homs_measure_xor_popcount_rate"]
+
+_sig("homs_model_create", [_P, _i32, _i32, _P, _P, _P, _P, ctypes.POINTER(_P)])
+_sig("homs_model_destroy", [_P], None)
+_sig("homs_model_set_weights", [_P, _P, _P, _P, _P])
+_sig("homs_model_get_weights", [_P, _P, _P, _P, _P])
+_sig("homs_model_embed", [_P, _i64, _P, _P, _P])
+_sig("homs_model_gradients", [_P, _i32, _P, _P, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                              _P, _P, _P, _P, _P])
+_sig("homs_model_train_step", [_P, _i32, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P])
+_sig("homs_model_embed_library", [_P, _P])
+_sig("homs_search_learned", [_P, _P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P,
+                             _P, _P])
 
 _sig("homs_measure_xor_popcount_rate", [_i32, ctypes.POINTER(ctypes.c_double)])
 
@@ -455,3 +470,121 @@ def to_device_csr(off, bins, levels, device):
     return (torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).to(device),
             torch.from_numpy(np.ascontiguousarray(bins, dtype=np.int32)).to(device),
             torch.from_numpy(np.ascontiguousarray(levels, dtype=np.uint8)).to(device))
+
+
+WEIGHT_NAMES = ("W1", "b1", "W2", "b2")
+
+
+class Model:
+    """A homs_model (learned shortlist) on a context's device.
+
+    weights: dict of float32 host arrays W1 [hidden, D], b1 [hidden],
+    W2 [embed, hidden], b2 [embed] (the initial weights are the caller's)."""
+
+    def __init__(self, ctx: Context, weights: dict):
+        self.ctx = ctx
+        self.hidden, self.dim = weights["W1"].shape
+        self.embed = weights["W2"].shape[0]
+        if self.dim != ctx.params.dim:
+            raise ValueError("W1 must be [hidden, D]")
+        w = self._host(weights)
+        h = _P()
+        ctx._ck(_lib.homs_model_create(ctx._h, self.hidden, self.embed,
+                                       *[_np_ptr(w[k]) for k in WEIGHT_NAMES], ctypes.byref(h)))
+        self._h = h
+
+    def _host(self, weights):
+        shapes = {"W1": (self.hidden, self.dim), "b1": (self.hidden,),
+                  "W2": (self.embed, self.hidden), "b2": (self.embed,)}
+        out = {}
+        for k in WEIGHT_NAMES:
+            a = np.ascontiguousarray(weights[k], dtype=np.float32)
+            if a.shape != shapes[k]:
+                raise ValueError(f"{k} must have shape {shapes[k]}")
+            out[k] = a
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.homs_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, weights: dict):
+        w = self._host(weights)
+        self.ctx._ck(_lib.homs_model_set_weights(self._h, *[_np_ptr(w[k]) for k in WEIGHT_NAMES]))
+
+    def get_weights(self) -> dict:
+        w = {"W1": np.zeros((self.hidden, self.dim), np.float32),
+             "b1": np.zeros(self.hidden, np.float32),
+             "W2": np.zeros((self.embed, self.hidden), np.float32),
+             "b2": np.zeros(self.embed, np.float32)}
+        self.ctx._ck(_lib.homs_model_get_weights(self._h, *[_np_ptr(w[k]) for k in WEIGHT_NAMES]))
+        return w
+
+    def embed(self, hv, out=None):
+        """homs_model_embed -> float32 [n, embed] unit embeddings."""
+        import torch
+        dev = self.ctx.device
+        n = hv.shape[0]
+        if out is None:
+            out = torch.empty((n, self.embed), dtype=torch.float32, device=dev)
+        self.ctx._ck(_lib.homs_model_embed(self._h, n, _dptr(hv, torch.int32, "hv", dev),
+                                           _dptr(out, torch.float32, "out", dev), _stream(dev)))
+        return out
+
+    def gradients(self, q_hv, r_hv, tau: float):
+        """homs_model_gradients -> (loss, {W1, b1, W2, b2} gradients) without an update."""
+        import torch
+        dev = self.ctx.device
+        g = {"W1": np.zeros((self.hidden, self.dim), np.float32),
+             "b1": np.zeros(self.hidden, np.float32),
+             "W2": np.zeros((self.embed, self.hidden), np.float32),
+             "b2": np.zeros(self.embed, np.float32)}
+        loss = ctypes.c_float(0.0)
+        self.ctx._ck(_lib.homs_model_gradients(
+            self._h, q_hv.shape[0], _dptr(q_hv, torch.int32, "q_hv", dev),
+            _dptr(r_hv, torch.int32, "r_hv", dev), tau, ctypes.byref(loss),
+            *[_np_ptr(g[k]) for k in WEIGHT_NAMES], _stream(dev)))
+        return loss.value, g
+
+    def train_step(self, q_hv, r_hv, tau: float, lr: float, loss_out=None):
+        """homs_model_train_step; returns the device float32 [1] loss tensor."""
+        import torch
+        dev = self.ctx.device
+        if loss_out is None:
+            loss_out = torch.empty(1, dtype=torch.float32, device=dev)
+        self.ctx._ck(_lib.homs_model_train_step(
+            self._h, q_hv.shape[0], _dptr(q_hv, torch.int32, "q_hv", dev),
+            _dptr(r_hv, torch.int32, "r_hv", dev), tau, lr,
+            _dptr(loss_out, torch.float32, "loss", dev), _stream(dev)))
+        return loss_out
+
+    def embed_library(self):
+        self.ctx._ck(_lib.homs_model_embed_library(self._h, _stream(self.ctx.device)))
+
+    def search(self, q_hv, pmz, charge, k: int, kind=TOL_DA, value=500.0, shortlist=False):
+        """homs_search_learned -> (idx int64, dist int32, fallback uint8[, shortlist int64 [nq, k]])."""
+        import torch
+        c = self.ctx
+        dev = c.device
+        nq = pmz.shape[0]
+        if q_hv.shape != (nq, c.words):
+            raise ValueError("q_hv must be [nq, D/32]")
+        idx = torch.empty(nq, dtype=torch.int64, device=dev)
+        dist = torch.empty(nq, dtype=torch.int32, device=dev)
+        fb = torch.empty(nq, dtype=torch.uint8, device=dev)
+        sl = torch.empty((nq, k), dtype=torch.int64, device=dev) if shortlist else None
+        w = c._win(kind, value)
+        c._ck(_lib.homs_search_learned(
+            c._h, self._h, nq, _dptr(q_hv, torch.int32, "q_hv", dev),
+            _dptr(pmz, torch.float64, "pmz", dev), _dptr(charge, torch.int8, "charge", dev),
+            ctypes.byref(w), k, _dptr(idx, torch.int64, "idx", dev),
+            _dptr(dist, torch.int32, "dist", dev), _dptr(fb, torch.uint8, "fallback", dev),
+            _dptr(sl, torch.int64, "shortlist", dev) if shortlist else None, _stream(dev)))
+        return (idx, dist, fb, sl) if shortlist else (idx, dist, fb)

@@ -1,0 +1,359 @@
+"""Learned shortlist on the GPU (through the C ABI) against the float64 MLP
+oracle: embeddings, loss and gradients, the Adam step, training, and the
+shortlist search (validity of each shortlist against oracle scores, exact
+rescoring, fallback, and the exhaustive case k >= window).
+
+The GPU stores weights and hidden activations in bfloat16 and accumulates
+in float32; the oracle is evaluated with the same bfloat16 roundings
+(mlp.rounded_weights, round_hidden=True) in float64, so the remaining
+differences are float32 accumulation and rare bfloat16 rounding-boundary
+flips of the hidden layer. Tolerances:
+  embeddings   |e_gpu - e_oracle| <= 1e-3 per element, row norm <= 5e-3
+               (against the unrounded float64 oracle: row norm <= 3e-2)
+  gradients    ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-2 per parameter
+  scores       members of a shortlist score at least the oracle's k-th score
+               minus 1e-2 and non-members at most that score plus 1e-2
+               (two unit embeddings each within 5e-3 of the oracle's)
+  rescoring    exact: (distance, index) = the lexicographic minimum over the
+               returned shortlist of the oracle's Hamming distances.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
+
+import oracle  # noqa: E402
+from oracle import mlp  # noqa: E402
+from synth import WORKLOADS, make_workload  # noqa: E402
+
+TAU = 0.1
+SCORE_TOL = 1e-2
+
+
+def _h():
+    import paper_2211_16422_amd.hyperoms as h
+    return h
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _weights(D, H, E, seed):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(D, H, E, rng)
+    p["b1"] = rng.normal(0, 0.05, H)
+    p["b2"] = rng.normal(0, 0.05, E)
+    return {k: v.astype(np.float32) for k, v in p.items()}
+
+
+def _f64(p):
+    return {k: v.astype(np.float64) for k, v in p.items()}
+
+
+def _rand_hv(n, D, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2 ** 32, (n, D // 32), dtype=np.uint64).astype(np.uint32)
+
+
+def _oracle_embed(p32, hv, D, round_out=False):
+    e = mlp.embed(mlp.rounded_weights(_f64(p32)), mlp.bipolar(hv, D), round_hidden=True)
+    return mlp.round_bf16(e) if round_out else e
+
+
+@pytest.mark.parametrize("D,H,E,n", [(2048, 256, 64, 333), (8192, 1024, 256, 200)])
+def test_embed_matches_oracle(D, H, E, n):
+    h = _h()
+    ctx = h.Context(h.Params(dim=D))
+    p = _weights(D, H, E, seed=D + n)
+    m = h.Model(ctx, p)
+    hv = _rand_hv(n, D, seed=n)
+    e = m.embed(_dev(hv.view(np.int32))).cpu().numpy().astype(np.float64)
+    want = _oracle_embed(p, hv, D)
+    assert np.abs(e - want).max() <= 1e-3
+    assert np.linalg.norm(e - want, axis=1).max() <= 5e-3
+    exact = mlp.embed(_f64(p), mlp.bipolar(hv, D))
+    assert np.linalg.norm(e - exact, axis=1).max() <= 3e-2
+    assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-5)
+    w = m.get_weights()
+    assert all(np.array_equal(w[k], p[k]) for k in p)
+    m.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("D,H,E,B", [(2048, 256, 64, 64), (8192, 1024, 256, 96)])
+def test_gradients_match_oracle(D, H, E, B):
+    h = _h()
+    ctx = h.Context(h.Params(dim=D))
+    p = _weights(D, H, E, seed=B)
+    m = h.Model(ctx, p)
+    q = _rand_hv(B, D, seed=1)
+    r = q ^ _rand_hv(B, D, seed=2) & _rand_hv(B, D, seed=3) & _rand_hv(B, D, seed=4)
+    loss, g = m.gradients(_dev(q.view(np.int32)), _dev(r.view(np.int32)), TAU)
+    o_loss, o_g = mlp.loss_and_grads(mlp.rounded_weights(_f64(p)), mlp.bipolar(q, D),
+                                     mlp.bipolar(r, D), TAU, round_hidden=True)
+    assert abs(loss - o_loss) <= 1e-3 * abs(o_loss) + 1e-4
+    for k in ("W1", "b1", "W2", "b2"):
+        rel = np.linalg.norm(g[k] - o_g[k]) / np.linalg.norm(o_g[k])
+        assert rel <= 1e-2, (k, rel)
+    m.close()
+    ctx.close()
+
+
+def test_adam_step_matches_oracle():
+    """One train step = the oracle's gradients followed by Adam: on the first
+    step every update is -lr * sign(g) unless g is tiny, so elements with a
+    clear gradient must land on the oracle's value."""
+    D, H, E, B, lr = 2048, 256, 64, 64, 1e-3
+    h = _h()
+    ctx = h.Context(h.Params(dim=D))
+    p = _weights(D, H, E, seed=11)
+    m = h.Model(ctx, p)
+    q = _rand_hv(B, D, seed=5)
+    r = q ^ (_rand_hv(B, D, seed=6) & _rand_hv(B, D, seed=7))
+    import torch
+    loss = m.train_step(_dev(q.view(np.int32)), _dev(r.view(np.int32)), TAU, lr)
+    torch.cuda.synchronize()
+    w1 = m.get_weights()
+    o_loss, o_g = mlp.loss_and_grads(mlp.rounded_weights(_f64(p)), mlp.bipolar(q, D),
+                                     mlp.bipolar(r, D), TAU, round_hidden=True)
+    assert abs(float(loss.item()) - o_loss) <= 1e-3 * abs(o_loss) + 1e-4
+    want = mlp.adam(_f64(p), o_g, {}, lr)
+    for k in ("W1", "b1", "W2", "b2"):
+        clear = np.abs(o_g[k]) > 1e-2 * np.abs(o_g[k]).max()
+        err = np.abs(w1[k].astype(np.float64) - want[k])
+        assert err[clear].max() <= 1e-6 + 1e-6 * np.abs(want[k][clear]).max(), k
+        moved = np.abs(w1[k].astype(np.float64) - p[k])
+        assert moved.max() <= lr * (1 + 1e-3), k
+        assert np.mean(err <= 1e-6 + 1e-6 * np.abs(want[k])) >= 0.95, k
+    m.close()
+    ctx.close()
+
+
+def test_training_lowers_the_loss():
+    D, H, E, B = 2048, 256, 64, 128
+    h = _h()
+    import torch
+    ctx = h.Context(h.Params(dim=D))
+    m = h.Model(ctx, _weights(D, H, E, seed=12))
+    q = _rand_hv(B, D, seed=8)
+    r = q ^ (_rand_hv(B, D, seed=9) & _rand_hv(B, D, seed=10) & _rand_hv(B, D, seed=13))
+    qd, rd = _dev(q.view(np.int32)), _dev(r.view(np.int32))
+    first = m.gradients(qd, rd, TAU)[0]
+    losses = []
+    for _ in range(40):
+        losses.append(m.train_step(qd, rd, TAU, 2e-3).clone())
+    torch.cuda.synchronize()
+    losses = [float(x.item()) for x in losses]
+    assert abs(losses[0] - first) <= 1e-3 * abs(first) + 1e-4
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.5 * first, (first, losses[-1])
+    m.close()
+    ctx.close()
+
+
+class LearnedSetup:
+    """Workload encoded by both sides; a model with seeded weights."""
+
+    def __init__(self, n_ref=2000, n_query=200, seed=0, D=2048, H=256, E=64, n_train=0):
+        h = _h()
+        self.D = D
+        self.g = make_workload(WORKLOADS["tiny"], n_ref=n_ref, n_query=n_query, seed=seed,
+                               n_train=n_train)
+        self.op = oracle.Params(dim=D)
+        idt, lvt = oracle.codebook(self.op)
+        lib, q = self.g.library, self.g.queries
+        self.o_lib = oracle.encode_raw(self.op, idt, lvt, lib)
+        self.o_q = oracle.encode_raw(self.op, idt, lvt, q)
+        self.ctx = h.Context(h.Params(dim=D))
+        hp = self.ctx.params
+        lo, lb, ll = h.preprocess(hp, lib.offsets, lib.mz, lib.intensity)
+        qo, qb, ql = h.preprocess(hp, q.offsets, q.mz, q.intensity)
+        self.ctx.encode_library(*h.to_device_csr(lo, lb, ll, "cuda:0"), _dev(lib.pmz),
+                                _dev(lib.charge))
+        self.q_hv = self.ctx.encode_queries(*h.to_device_csr(qo, qb, ql, "cuda:0"))
+        self.q_pmz, self.q_ch = _dev(q.pmz), _dev(q.charge)
+        self.p = _weights(D, H, E, seed=seed + 100)
+        self.model = h.Model(self.ctx, self.p)
+        self.model.embed_library()
+
+    def oracle_scores(self, p=None):
+        p = self.p if p is None else p
+        El = _oracle_embed(p, self.o_lib, self.D, round_out=True)
+        Eq = _oracle_embed(p, self.o_q, self.D, round_out=True)
+        return El, Eq
+
+    def windows(self, tol_da):
+        lib, q = self.g.library, self.g.queries
+        out = []
+        for i in range(q.n):
+            lo, hi = q.pmz[i] - tol_da, q.pmz[i] + tol_da
+            out.append(np.flatnonzero((lib.charge == q.charge[i]) & (lib.pmz >= lo)
+                                      & (lib.pmz <= hi)))
+        return out
+
+    def close(self):
+        self.model.close()
+        self.ctx.close()
+
+
+@pytest.fixture(scope="module")
+def tiny_learned():
+    s = LearnedSetup()
+    yield s
+    s.close()
+
+
+def _check_shortlists(s, k, tol_da, idx, dist, fb, sl, El, Eq):
+    """Every non-fallback shortlist is a valid top-k of the oracle scores (up
+    to SCORE_TOL) and the result is the exact minimum over it."""
+    wins = s.windows(tol_da)
+    n_checked = 0
+    for i, W in enumerate(wins):
+        if fb[i]:
+            continue
+        n = min(k, W.size)
+        row = sl[i]
+        assert (row[n:] == -1).all(), i
+        mem = row[:n]
+        assert (mem >= 0).all() and np.unique(mem).size == n, i
+        assert np.isin(mem, W).all(), i
+        if W.size == 0:
+            assert idx[i] == -1 and dist[i] == -1
+            continue
+        sc = El[W] @ Eq[i]
+        kth = np.sort(sc)[::-1][n - 1]
+        s_mem = El[mem] @ Eq[i]
+        assert s_mem.min() >= kth - SCORE_TOL, i
+        rest = np.setdiff1d(W, mem)
+        if rest.size:
+            assert (El[rest] @ Eq[i]).max() <= kth + SCORE_TOL, i
+        hd = np.bitwise_count(s.o_lib[mem] ^ s.o_q[i]).sum(axis=1)
+        j = np.lexsort((mem, hd))[0]
+        assert (idx[i], dist[i]) == (mem[j], hd[j]), i
+        n_checked += 1
+    return n_checked
+
+
+@pytest.mark.parametrize("k", [16, 64, 256])
+def test_shortlists_are_valid_top_k(tiny_learned, k):
+    s = tiny_learned
+    idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k, value=500.0, shortlist=True)
+    idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
+    assert (fb == 0).all()  # every window here is within the unsampled size
+    El, Eq = s.oracle_scores()
+    assert _check_shortlists(s, k, 500.0, idx, dist, fb, sl, El, Eq) == s.g.queries.n - int(
+        sum(w.size == 0 for w in s.windows(500.0)))
+
+
+@pytest.mark.parametrize("kind,value", [(0, 50.0), (1, 20.0), (0, 0.0)])
+def test_shortlist_covering_the_window_is_exact(tiny_learned, kind, value):
+    """With k at least every window's size the shortlist is the whole window
+    and the result must equal the exhaustive oracle search bit for bit."""
+    s = tiny_learned
+    g = s.g
+    cnt = oracle.window_counts(g.library.pmz, g.library.charge, g.queries.pmz, g.queries.charge,
+                               kind, value)
+    k = 1024
+    assert cnt.max() <= k
+    idx, dist, fb = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k, kind=kind, value=value)
+    o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
+                                  g.queries.pmz, g.queries.charge, kind, value)
+    assert np.array_equal(idx.cpu().numpy(), o_idx)
+    assert np.array_equal(dist.cpu().numpy(), o_dist)
+    assert (fb.cpu().numpy() == 0).all()
+
+
+def test_stale_library_embeddings_are_refused(tiny_learned):
+    s = tiny_learned
+    h = _h()
+    import torch
+    m = h.Model(s.ctx, s.p)
+    with pytest.raises(h.HomsError) as e:
+        m.search(s.q_hv, s.q_pmz, s.q_ch, 16)
+    assert e.value.status == h.HOMS_E_STATE
+    m.embed_library()
+    r = _rand_hv(32, s.D, seed=1)
+    m.train_step(_dev(r.view(np.int32)), _dev(r.view(np.int32)), TAU, 1e-3)
+    with pytest.raises(h.HomsError):
+        m.search(s.q_hv, s.q_pmz, s.q_ch, 16)
+    with pytest.raises(h.HomsError):
+        s.model.search(s.q_hv, s.q_pmz, s.q_ch, 2000)  # k above the limit
+    torch.cuda.synchronize()
+    m.close()
+
+
+def test_sampled_threshold_windows():
+    """Windows larger than the unsampled size (library of 40,000): the
+    threshold comes from a sample; queries that fall back must carry the
+    exhaustive answer and every other shortlist must be a valid top-k."""
+    s = LearnedSetup(n_ref=20000, n_query=300, seed=4)
+    try:
+        g = s.g
+        cnt = oracle.window_counts(g.library.pmz, g.library.charge, g.queries.pmz,
+                                   g.queries.charge, 0, 500.0)
+        assert (cnt > 4096).mean() > 0.5  # most windows take the sampled path
+        for k in (16, 64):
+            idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k, value=500.0,
+                                               shortlist=True)
+            idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
+            assert fb.mean() <= 0.05, fb.mean()
+            El, Eq = s.oracle_scores()
+            _check_shortlists(s, k, 500.0, idx, dist, fb, sl, El, Eq)
+            o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge,
+                                          s.o_q, g.queries.pmz, g.queries.charge, 0, 500.0)
+            f = fb.astype(bool)
+            assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
+            assert (sl[f] == -1).all()
+    finally:
+        s.close()
+
+
+def test_training_raises_agreement():
+    """Trained on (query, exact top-1) pairs of separate training queries,
+    the model's k = 8 shortlist finds the exact top-1 of held-out queries more
+    often than the untrained model does."""
+    import torch
+    h = _h()
+    s = LearnedSetup(n_query=400, seed=6, n_train=4096)
+    try:
+        g = s.g
+        o_idx, _ = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
+                                 g.queries.pmz, g.queries.charge, 0, 500.0)
+        k = 8
+
+        def agreement():
+            s.model.embed_library()
+            idx, _, fb = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k)
+            has = o_idx >= 0
+            return float(np.mean(idx.cpu().numpy()[has] == o_idx[has]))
+
+        before = agreement()
+        tr = g.train
+        hp = s.ctx.params
+        to, tb, tl = h.preprocess(hp, tr.offsets, tr.mz, tr.intensity)
+        t_hv = s.ctx.encode_queries(*h.to_device_csr(to, tb, tl, "cuda:0"))
+        t_idx, _ = s.ctx.search_window(t_hv, _dev(tr.pmz), _dev(tr.charge))
+        lib_rows = s.ctx.library_export()
+        keep = torch.nonzero(t_idx >= 0).flatten()
+        q_rows = t_hv[keep].contiguous()
+        r_rows = lib_rows[t_idx[keep]].contiguous()
+        B = 256
+        n = (q_rows.shape[0] // B) * B
+        gen = torch.Generator(device="cpu").manual_seed(0)
+        for epoch in range(6):
+            perm = torch.randperm(q_rows.shape[0], generator=gen)[:n].to("cuda:0")
+            for b0 in range(0, n, B):
+                sel = perm[b0:b0 + B]
+                s.model.train_step(q_rows[sel].contiguous(), r_rows[sel].contiguous(), 0.05,
+                                   1e-3)
+        torch.cuda.synchronize()
+        after = agreement()
+        print(f"top-1 agreement at k={k}: untrained {before:.3f}, trained {after:.3f}")
+        assert after > before + 0.05, (before, after)
+    finally:
+        s.close()

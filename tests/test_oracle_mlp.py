@@ -107,3 +107,30 @@ def test_shortlist_search_brute_force():
             assert idx[i] == best
         else:
             assert (idx[i], dist[i]) == (-1, -1)
+
+
+def test_round_bf16_known_values():
+    """bfloat16 keeps 8 significant bits: 1 + 2^-8 lies halfway between 1 and
+    1 + 2^-7 and goes to the even one (1); 1 + 3 * 2^-9 is nearer 1 + 2^-7;
+    exact bfloat16 values and signs pass through; 2^-133 is subnormal in
+    float32 and exact in bfloat16."""
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -9, -(1 + 2.0 ** -7), 0.0, 3.0,
+                  1 + 2.0 ** -8 + 2.0 ** -20, 2.0 ** -133, 65280.0, 65408.0])
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -7, -(1 + 2.0 ** -7), 0.0, 3.0, 1 + 2.0 ** -7,
+                     2.0 ** -133, 65280.0, 65536.0])
+    assert np.array_equal(mlp.round_bf16(x), want)
+
+
+def test_round_hidden_forward_differs_only_by_bf16_rounding():
+    """With rounding off the forward is unchanged; with it on, h is the
+    nearest bfloat16 of the exact h (relative error at most half a unit in
+    the last place, 2^-8 of the value)."""
+    rng = np.random.default_rng(5)
+    p = mlp.init_params(256, 64, 32, rng)
+    X = 1.0 - 2.0 * rng.integers(0, 2, (7, 256))
+    a, b = mlp.forward(p, X), mlp.forward(p, X, round_hidden=True)
+    assert np.allclose(a["a1"], b["a1"], rtol=0, atol=0)
+    nz = a["h"] != 0
+    rel = np.abs(b["h"][nz] - a["h"][nz]) / np.abs(a["h"][nz])
+    assert rel.max() <= 2.0 ** -8 and (b["h"][~nz] == 0).all()
+    assert not np.array_equal(a["h"], b["h"])
