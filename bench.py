@@ -7,7 +7,11 @@ Workload (default "large"): a synthetic library of 1,000,000 references plus
 +-500 Da with charge matching. The library is preprocessed, uploaded and
 encoded once before timing (reference hypervectors are encoded once and
 reused, Section 3.3). One step = encode all query spectrum vectors (already
-resident in HBM) + open-window Hamming top-1 search of every query.
+resident in HBM) + open-window Hamming top-1 search of every query. The
+search is exact with every engine; the default engine computes the bipolar
+dot products on matrix cores (fp8 e4m3 +-1, fp32 accumulation, which is exact
+for these integers), and the XOR + popcount and int8 engines are timed beside
+it on the same queries.
 
 Prints one JSON line: comparisons/s (sum of candidate-window sizes per
 second), queries/s, the roofline of the search kernel measured with HIP
@@ -36,20 +40,23 @@ METRIC = "query-ref Hamming comparisons/s and queries/s at ±500 Da, D=8192"
 VALU_MODEL_TOPS = 256 * 64 * 2.4e9 / 1e12
 MFMA_PEAK_TOPS = 5000.0  # dense fp8 / int8 matrix peak of MI355X, TFLOP/s (TOP/s)
 
-# HBM bytes per launch of the search kernel on the default large workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
-# (profiles/search_popcount_large.md). Valid only while the kernel source has
-# the hash it was measured on.
-MEASURED_TRAFFIC = {"a5ee47bd0896dc11": 4.868e12}
+# HBM bytes per launch of each search kernel on the default large workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
+# (profiles/search_popcount_large.md). Keyed by engine and the hash of the
+# kernel's sources: valid only while the source is the one measured.
+MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12}
+
+ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
+                  "mfma_fp8": ("search_mfma.hip",), "mfma_int8": ("search_mfma.hip",)}
 
 
 VALU_PEAK_TOPS = VALU_MODEL_TOPS  # replaced by the live measurement in main()
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(engine: str = "popcount") -> str:
     import hashlib
     digest = hashlib.sha256()
-    for name in ("search_popc.hip", "popcount_tile.h"):
+    for name in ENGINE_SOURCES[engine]:
         with open(os.path.join(ROOT, "paper_2211_16422_amd", "csrc", name), "rb") as fh:
             digest.update(fh.read())
     return digest.hexdigest()[:16]
@@ -64,18 +71,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=["tiny", "large", "batched"])
+    ap.add_argument("--workload", default="large",
+                    choices=["tiny", "large", "batched", "learned"])
     ap.add_argument("--n-ref", type=int, default=None, help="override reference count")
     ap.add_argument("--n-query", type=int, default=None, help="override query count")
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="queries in the oracle's timed sample (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baseline (for profiler runs)")
+    ap.add_argument("--engine", default="mfma_fp8", choices=list(ENGINE_SOURCES),
+                    help="search engine of the timed step (all three are bit-exact)")
     ap.add_argument("--skip-mfma", action="store_true",
-                    help="do not time the matrix-core (precision) form")
+                    help="time only the step's engine (no side-by-side engine timings)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES bytes (a reference "
                          "kernel for scaling hardware byte counters)")
+    ap.add_argument("--n-train", type=int, default=None, help="learned: training queries")
+    ap.add_argument("--k", type=int, default=64, help="learned: shortlist size")
+    ap.add_argument("--epochs", type=int, default=2, help="learned: training epochs")
+    ap.add_argument("--batch", type=int, default=4096, help="learned: training pairs per step")
+    ap.add_argument("--lr", type=float, default=1e-3, help="learned: Adam learning rate")
+    ap.add_argument("--tau", type=float, default=0.05, help="learned: InfoNCE temperature")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -97,6 +113,8 @@ def main():
     dev = torch.device("cuda", 0)
     if w.name == "batched":
         return bench_batched(args, w, dev)
+    if w.name == "learned":
+        return bench_learned(args, w, dev)
     t0 = time.time()
     g = make_workload(w, n_ref=args.n_ref, n_query=args.n_query)
     lib, q = g.library, g.queries
@@ -132,9 +150,13 @@ def main():
     out_idx = torch.empty(q.n, dtype=torch.int64, device=dev)
     out_dist = torch.empty(q.n, dtype=torch.int32, device=dev)
 
+    engines = {"popcount": h.ENGINE_POPCOUNT, "mfma_fp8": h.ENGINE_MFMA_F8,
+               "mfma_int8": h.ENGINE_MFMA_I8}
+    engine = engines[args.engine]
+
     def step():
         ctx.encode_queries(*q_dev, out=q_hv)
-        ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, h.ENGINE_POPCOUNT,
+        ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine,
                           out_idx=out_idx, out_dist=out_dist)
 
     if args.copy_calibration > 0:
@@ -161,42 +183,59 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile_enable(False)
-    log(f"timed {args.steps} steps in {elapsed:.3f}s; search kernel "
+    log(f"timed {args.steps} steps in {elapsed:.3f}s; {args.engine} search kernel "
         f"{prof['search_ms'] / max(prof['search_launches'], 1):.2f} ms per launch")
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = pairs * args.steps / elapsed
     qps = q.n * args.steps / elapsed
     words = w.dim // 32
-    search_ms = prof["search_ms"] / max(prof["search_launches"], 1)
-    ops_per_launch = 2.0 * words * pairs  # v_xor_b32 + v_bcnt_u32_b32 per word per pair
-    achieved = ops_per_launch / (search_ms * 1e-3) / 1e12
     default_shape = args.n_ref is None and args.n_query is None and w.name == "large"
-    traffic = MEASURED_TRAFFIC.get(kernel_source_hash()) if default_shape else None
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                "peak_kind": "measured xor+popcount issue rate (homs_measure_xor_popcount_rate)",
-                "peak_issue_model": round(VALU_MODEL_TOPS, 3),
-                "kernel": "search_popcount_kernel", "kernel_ms": round(search_ms, 3),
-                "ops_per_pair": 2 * words}
 
+    def roofline_of(name, kernel_ms):
+        traffic = (MEASURED_TRAFFIC.get((name, kernel_source_hash(name)))
+                   if default_shape else None)
+        if name == "popcount":
+            ops = 2.0 * words * pairs  # v_xor_b32 + v_bcnt_u32_b32 per word per pair
+            ach = ops / (kernel_ms * 1e-3) / 1e12
+            return {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                    "unit": "TOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                    "peak_kind": "measured xor+popcount issue rate "
+                                 "(homs_measure_xor_popcount_rate)",
+                    "peak_issue_model": round(VALU_MODEL_TOPS, 3),
+                    "kernel": "search_popcount_kernel", "kernel_ms": round(kernel_ms, 3),
+                    "ops_per_pair": 2 * words}
+        ops = 2.0 * w.dim * pairs  # one multiply-add per component per pair
+        ach = ops / (kernel_ms * 1e-3) / 1e12
+        fmt = "fp8 e4m3" if name == "mfma_fp8" else "int8"
+        return {"bound": "mfma", "achieved": round(ach, 1), "peak": MFMA_PEAK_TOPS,
+                "unit": "TFLOP/s" if name == "mfma_fp8" else "TOP/s",
+                "frac": round(ach / MFMA_PEAK_TOPS, 4), "traffic": traffic,
+                "peak_kind": f"dense {fmt} matrix peak of MI355X",
+                "kernel": f"mfma_search_kernel<{fmt}>", "kernel_ms": round(kernel_ms, 3),
+                "ops_per_pair": 2 * w.dim}
+
+    search_ms = prof["search_ms"] / max(prof["search_launches"], 1)
+    roofline = roofline_of(args.engine, search_ms)
     res_idx = out_idx.cpu().numpy()
     res_dist = out_dist.cpu().numpy()
 
-    # precision form: the same search on matrix cores (fp8 e4m3 and int8 +-1)
+    # the other engines on the same queries: same results, their own rooflines
     forms = {}
     if not args.skip_mfma:
-        for name, engine in (("mfma_fp8", h.ENGINE_MFMA_F8), ("mfma_int8", h.ENGINE_MFMA_I8)):
+        for name, eng in engines.items():
+            if name == args.engine:
+                continue
             m_idx = torch.empty_like(out_idx)
             m_dist = torch.empty_like(out_dist)
-            ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine, m_idx, m_dist)
+            ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, eng, m_idx, m_dist)
             torch.cuda.synchronize()
             ctx.profile_enable(True)
             ctx.profile_read()
             reps = max(1, args.steps)
             t0 = time.perf_counter()
             for _ in range(reps):
-                ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine, m_idx, m_dist)
+                ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, eng, m_idx, m_dist)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             pm = ctx.profile_read()
@@ -204,15 +243,10 @@ def main():
             kms = pm["search_ms"] / max(pm["search_launches"], 1)
             same = bool(np.array_equal(m_idx.cpu().numpy(), res_idx) and
                         np.array_equal(m_dist.cpu().numpy(), res_dist))
-            tops = 2.0 * w.dim * pairs / (kms * 1e-3) / 1e12
-            forms[name] = {"comparisons_per_s": pairs * reps / el, "kernel_ms": round(kms, 3),
-                           "achieved": round(tops, 1), "peak": MFMA_PEAK_TOPS,
-                           "unit": "TOP/s", "frac": round(tops / MFMA_PEAK_TOPS, 4),
-                           "vs_popcount_valu_roofline": round(
-                               pairs / (kms * 1e-3) / (VALU_PEAK_TOPS * 1e12 / (2 * words)), 3),
-                           "bit_exact_vs_popcount": same}
-            log(f"{name}: search kernel {kms:.2f} ms ({tops:.0f} TOP/s, "
-                f"{tops / MFMA_PEAK_TOPS:.1%} of peak), identical to popcount: {same}")
+            forms[name] = {"comparisons_per_s": pairs * reps / el,
+                           "roofline": roofline_of(name, kms),
+                           f"bit_exact_vs_{args.engine}": same}
+            log(f"{name}: search kernel {kms:.2f} ms, identical to {args.engine}: {same}")
     cpu = None
     parity = None
     if args.cpu_sample > 0 and not args.profile_only:
@@ -221,19 +255,23 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "comparisons/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"popcount": "u32", "mfma_fp8": "fp8e4m3(+-1)->f32",
+                  "mfma_int8": "i8(+-1)->i32"}[args.engine],
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {g.meta['n_ref']} references + {g.meta['n_decoy']} "
                                f"decoys, {q.n} queries, D={w.dim}, Q={w.n_levels}, "
                                f"0.05 Da bins, +-500 Da, charge-matched",
                    "library": lib.n, "queries": q.n, "dim": w.dim, "pairs_per_step": pairs,
-                   "step": "encode queries + open-window Hamming top-1 (XOR+popcount)"},
+                   "engine": args.engine,
+                   "step": "encode queries + open-window Hamming top-1 (exact; "
+                           f"{args.engine} engine)"},
         "queries_per_s": qps,
         "library_encode_s": lib_encode_s,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
-        "precision_form": forms,
+        "other_engines": forms,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -337,6 +375,149 @@ def bench_batched(args, w, dev):
         "bit_exact_vs_search_window": same,
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_learned(args, w, dev):
+    """Learned shortlist: MLP D -> 1024 -> 256 trained on the GPU on (training
+    query, exact top-1) pairs; per query the top-k window candidates by
+    embedding score are rescored exactly, with exhaustive fallback. Reports
+    queries/s and window comparisons covered per second, top-1 agreement
+    with the exhaustive search and the speedup over it."""
+    import torch
+
+    import paper_2211_16422_amd.hyperoms as h
+    from synth import make_workload
+
+    t0 = time.time()
+    g = make_workload(w, n_ref=args.n_ref, n_query=args.n_query, n_train=args.n_train)
+    lib, q, tr = g.library, g.queries, g.train
+    log(f"generated {lib.n} library + {q.n} query + {tr.n} training spectra in "
+        f"{time.time() - t0:.1f}s")
+    hp = h.Params(dim=w.dim, n_levels=w.n_levels, bins_per_da=w.bins_per_da)
+    ctx = h.Context(hp, device=0)
+    l_dev = h.to_device_csr(*h.preprocess(hp, lib.offsets, lib.mz, lib.intensity), dev)
+    ctx.encode_library(*l_dev, torch.from_numpy(lib.pmz).to(dev),
+                       torch.from_numpy(lib.charge).to(dev))
+    del l_dev
+    q_hv = ctx.encode_queries(*h.to_device_csr(*h.preprocess(hp, q.offsets, q.mz,
+                                                             q.intensity), dev))
+    t_hv = ctx.encode_queries(*h.to_device_csr(*h.preprocess(hp, tr.offsets, tr.mz,
+                                                             tr.intensity), dev))
+    q_pmz, q_ch = torch.from_numpy(q.pmz).to(dev), torch.from_numpy(q.charge).to(dev)
+    t_pmz, t_ch = torch.from_numpy(tr.pmz).to(dev), torch.from_numpy(tr.charge).to(dev)
+    lo, hi = ctx.window_bounds(q_pmz, q_ch, h.TOL_DA, 500.0)
+    pairs = int((hi - lo).sum().item())
+    torch.cuda.synchronize()
+    log(f"encoded; {pairs:.4e} window pairs for {q.n} queries")
+
+    # exhaustive reference (and timing) on the evaluation queries
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    ex = {}
+    for name, engine in (("popcount", h.ENGINE_POPCOUNT), ("mfma_fp8", h.ENGINE_MFMA_F8)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e_idx, e_dist = ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine)
+        torch.cuda.synchronize()
+        ex[name] = time.perf_counter() - t0
+    ctx.profile_read()
+    log(f"exhaustive search: popcount {ex['popcount']:.2f}s, fp8 {ex['mfma_fp8']:.2f}s")
+
+    # training pairs: exact top-1 of the training queries, batched in m/z order
+    t0 = time.perf_counter()
+    t_idx, _ = ctx.search_window(t_hv, t_pmz, t_ch, h.TOL_DA, 500.0, h.ENGINE_MFMA_F8)
+    lib_rows = ctx.library_export()
+    order = torch.from_numpy(np.lexsort((tr.pmz, tr.charge))).to(dev)
+    order = order[t_idx[order] >= 0]
+    B = args.batch
+    nb = order.numel() // B
+    order = order[:nb * B]
+    tq = t_hv[order].contiguous()
+    tr_rows = lib_rows[t_idx[order]].contiguous()
+    del lib_rows
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    log(f"training labels: {order.numel()} pairs in {label_s:.1f}s")
+
+    rng = np.random.default_rng(12345)
+    H, E, D = 1024, 256, w.dim
+    wts = {"W1": (rng.uniform(-1, 1, (H, D)) / np.sqrt(D)).astype(np.float32),
+           "b1": np.zeros(H, np.float32),
+           "W2": (rng.uniform(-1, 1, (E, H)) / np.sqrt(H)).astype(np.float32),
+           "b2": np.zeros(E, np.float32)}
+    model = h.Model(ctx, wts)
+    has = e_idx >= 0
+
+    def evaluate(tag):
+        model.embed_library()
+        idx, dist, fb = model.search(q_hv, q_pmz, q_ch, args.k)
+        agree = float(((idx == e_idx) & (dist == e_dist))[has].float().mean().item())
+        fbr = float(fb.float().mean().item())
+        log(f"{tag}: top-1 agreement {agree:.4f}, fallback {fbr:.4f}")
+        return agree, fbr
+
+    agree0, _ = evaluate("untrained")
+    t0 = time.perf_counter()
+    losses = []
+    gen = torch.Generator().manual_seed(0)
+    for ep in range(args.epochs):
+        for b in torch.randperm(nb, generator=gen).tolist():
+            sl = slice(b * B, (b + 1) * B)
+            losses.append(model.train_step(tq[sl], tr_rows[sl], args.tau, args.lr).clone())
+        torch.cuda.synchronize()
+        log(f"epoch {ep + 1}/{args.epochs}: mean loss "
+            f"{torch.cat(losses[-nb:]).mean().item():.4f}")
+    train_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model.embed_library()
+    torch.cuda.synchronize()
+    embed_lib_s = time.perf_counter() - t0
+    agree, fbr = evaluate("trained")
+
+    for _ in range(args.warmup):
+        model.search(q_hv, q_pmz, q_ch, args.k)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        idx, dist, fb = model.search(q_hv, q_pmz, q_ch, args.k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    step_s = el / args.steps
+    score_ms = prof["score_ms"] / args.steps
+    flops = 2.0 * E * pairs  # one E-dim dot product per window pair
+    tflops = flops / (score_ms * 1e-3) / 1e12
+    line = {
+        "metric": "learned-shortlist open search: queries/s and window comparisons covered/s "
+                  f"at +-500 Da, D={D}, k={args.k}",
+        "value": q.n / step_s, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"learned: {g.meta['n_ref']} references + {g.meta['n_decoy']} "
+                               f"decoys, {q.n} queries, {order.numel()} training pairs, "
+                               f"D={D}, MLP {D}-{H}-{E}, k={args.k}",
+                   "pairs_per_step": pairs, "epochs": args.epochs, "batch": B,
+                   "lr": args.lr, "tau": args.tau},
+        "comparisons_covered_per_s": pairs / step_s,
+        "top1_agreement": agree, "top1_agreement_untrained": agree0, "fallback_rate": fbr,
+        "exhaustive_s": ex, "speedup_vs_popcount": ex["popcount"] / step_s,
+        "speedup_vs_mfma_fp8": ex["mfma_fp8"] / step_s,
+        "train_s": train_s, "train_steps": len(losses), "label_s": label_s,
+        "embed_library_s": embed_lib_s,
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4), "traffic": None,
+                     "kernel": "collect_kernel (bf16 scoring)", "kernel_ms": round(score_ms, 3),
+                     "flops_per_pair": 2 * E},
+        "phase_ms": {"search": prof["search_ms"] / args.steps,
+                     "prep_and_embed": prof["prep_ms"] / args.steps},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    model.close()
     ctx.close()
 
 

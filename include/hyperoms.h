@@ -294,7 +294,11 @@ homs_status homs_device_errors(homs_ctx *ctx, uint32_t *flags, void *stream);
  * and launch counts since the last read, and resets them.
  *  search_ms/search_launches: the Hamming search kernel (any engine);
  *  encode_ms/encode_launches: the encode kernel of homs_encode_queries;
- *  prep_ms: window, ordering and result kernels around the search kernel.
+ *  prep_ms: window, ordering and result kernels around the search kernel
+ *           (and the query embedding of homs_search_learned);
+ *  score_ms/score_launches: the matrix-core scoring kernel of
+ *           homs_search_learned (one launch per pass of queries); its time is
+ *           also part of search_ms.
  */
 typedef struct homs_profile {
     double search_ms;
@@ -302,6 +306,8 @@ typedef struct homs_profile {
     double prep_ms;
     int64_t search_launches;
     int64_t encode_launches;
+    double score_ms;
+    int64_t score_launches;
 } homs_profile;
 homs_status homs_profile_enable(homs_ctx *ctx, int32_t enable);
 homs_status homs_profile_read(homs_ctx *ctx, homs_profile *out);

@@ -883,7 +883,9 @@ homs_status homs_profile_read(homs_ctx* c, homs_profile* out)
     out->prep_ms = c->prof.ms[homs::kProfPrep];
     out->search_launches = c->prof.launches[homs::kProfSearch];
     out->encode_launches = c->prof.launches[homs::kProfEncode];
-    for (int k = 0; k < 3; ++k) {
+    out->score_ms = c->prof.ms[homs::kProfScore];
+    out->score_launches = c->prof.launches[homs::kProfScore];
+    for (int k = 0; k < 4; ++k) {
         c->prof.ms[k] = 0;
         c->prof.launches[k] = 0;
     }
@@ -1156,8 +1158,16 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
     HIP_TRY(c, homs::model_embed(m, nq, d_q_hv, nullptr, q_emb, s), "embedding kernels");
     hipEvent_t e1 = prof_mark(c, s);
+    homs::SpanHook hook;
+    if (c->prof.on) {
+        hook.user = c;
+        hook.mark = [](void* u, hipStream_t st) { return prof_mark((homs_ctx*)u, st); };
+        hook.span = [](void* u, hipEvent_t a, hipEvent_t b) {
+            prof_span((homs_ctx*)u, a, b, homs::kProfScore);
+        };
+    }
     HIP_TRY(c, homs::launch_search_learned(c, m, lscratch, plan, nq, d_q_hv, q_emb, qperm, w.lo,
-                                           w.hi, k, w.keys, d_out_fallback, shortlist, s),
+                                           w.hi, k, w.keys, d_out_fallback, shortlist, hook, s),
             "shortlist kernels");
     // exhaustive pass over the windows of the queries that fell back
     HIP_TRY(c, homs::launch_fallback_windows(nq, d_out_fallback, w.lo, w.hi, lo2, hi2, s),

@@ -46,7 +46,7 @@ struct GraphCache {
 };
 
 // Event-based kernel timing (homs_profile_*).
-enum ProfKind { kProfSearch = 0, kProfEncode = 1, kProfPrep = 2 };
+enum ProfKind { kProfSearch = 0, kProfEncode = 1, kProfPrep = 2, kProfScore = 3 };
 struct Profiler {
     bool on = false;
     struct Span {
@@ -55,8 +55,8 @@ struct Profiler {
     };
     std::vector<Span> pending;
     std::vector<hipEvent_t> pool;
-    double ms[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    double ms[4] = {0, 0, 0, 0};
+    int64_t launches[4] = {0, 0, 0, 0};
 };
 
 }  // namespace homs

@@ -44,6 +44,14 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
 // learned_search.hip: shortlist of k per query, exact rescoring; sets
 // fallback[q] = 1 where the shortlist could not be formed (the caller then
 // runs the exhaustive search for those queries)
+// Optional timing of the scoring kernel: mark() records an event on the
+// stream (or returns nullptr), span() files an interval between two marks.
+struct SpanHook {
+    void* user = nullptr;
+    hipEvent_t (*mark)(void* user, hipStream_t s) = nullptr;
+    void (*span)(void* user, hipEvent_t a, hipEvent_t b) = nullptr;
+};
+
 struct LearnedScratchPlan {
     int64_t batch;  // queries per collection pass
 };
@@ -54,7 +62,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
                                  const uint32_t* q_hv, const uint16_t* q_emb,
                                  const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
                                  int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
-                                 hipStream_t s);
+                                 const SpanHook& hook, hipStream_t s);
 // lo2/hi2 = the query's window where fallback[q] is set, else empty
 hipError_t launch_fallback_windows(int64_t nq, const uint8_t* fallback, const int64_t* lo,
                                    const int64_t* hi, int64_t* lo2, int64_t* hi2, hipStream_t s);

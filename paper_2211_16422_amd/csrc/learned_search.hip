@@ -10,8 +10,9 @@
 //  1. threshold: score a regular sample of the window (every 2^j-th row of
 //     the sorted library, so that neighbouring queries share sample rows in
 //     cache) on the VALU and take the r-th largest sample score, r chosen so
-//     that about min(kTargetMul * k, kCapacity / 2) window candidates are
-//     expected at or above it;
+//     that about min(kTargetMul * k, kCapacity / 4) window candidates are
+//     expected at or above it (a quarter of the buffer, so overflow needs a
+//     sample four times off its expectation);
 //     windows of at most kSample candidates keep everything;
 //  2. collect: score every (query, candidate) pair on matrix cores (bf16
 //     operands, fp32 accumulation, 128 library rows x 128 m/z-ordered queries
@@ -35,7 +36,7 @@ namespace {
 
 constexpr int kSample = 4096;    // most sampled candidates per window
 constexpr int kTargetMul = 16;   // expected candidates at or above the threshold:
-                                 // min(16 k, kCapacity / 2)
+                                 // min(16 k, kCapacity / 4)
 constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 4096;  // library rows per collection workgroup
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
     }
     __syncthreads();
     bitonic_desc(s, np);
-    const int64_t target = min((int64_t)kTargetMul * k, (int64_t)kCapacity / 2);
+    const int64_t target = min((int64_t)kTargetMul * k, (int64_t)kCapacity / 4);
     int64_t r = (target * ns + w - 1) / w;
     r = r < 1 ? 1 : (r > ns ? ns : r);
     if (threadIdx.x == 0) thr[p] = fkey_inv((uint32_t)(s[r - 1] >> 32));
@@ -345,7 +346,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
                                  const uint32_t* q_hv, const uint16_t* q_emb,
                                  const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
                                  int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
-                                 hipStream_t s)
+                                 const SpanHook& hook, hipStream_t s)
 {
     if (nq <= 0) return hipSuccess;
     const int E = m->E;
@@ -378,8 +379,10 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         e = launch_tile_bounds(nb, qperm + b0, lo, hi, kTileQ, tlo, thi, s);
         if (e != hipSuccess) return e;
         zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
+        hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
         collect_kernel<<<dim3((uint32_t)tiles, (uint32_t)max_chunks), 256, 0, s>>>(
             E, b0, b1, q_sorted, qperm, lo, hi, thr, tlo, thi, m->lib_emb, c->lib.orig, count, buf);
+        if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
                                                           shortlist, fallback);
         rescore_kernel<<<(uint32_t)((nb + 3) / 4), kThreads, 0, s>>>(

@@ -7,22 +7,25 @@
 // integer of magnitude at most D <= 32768, exactly representable in int32 and
 // in fp32, so both engines reproduce the popcount distances bit for bit.
 //
-// Work decomposition: as in the popcount kernel, a workgroup takes one tile
-// of 256 m/z-ordered queries and one chunk of its candidate rows, here in
-// blocks of 256 library rows (the M dimension). Eight waves form a 2 x 4
-// grid; each owns a 128-row x 64-query accumulator tile (4 x 2 tiles of
+// Work decomposition (both engines): as in the popcount kernel, a workgroup
+// takes one tile of 256 m/z-ordered queries and one chunk of its candidate
+// rows, in blocks of 256 library rows (the M dimension). Eight waves form a
+// 2 x 4 grid; each owns a 128-row x 64-query accumulator tile (4 x 2 tiles of
 // 32 x 32) in VGPRs, so two waves share every SIMD and one wave's bit
 // expansion overlaps the other's matrix instructions.
 //
-// Operands: the packed bits of the 256 rows and 256 queries are read from
-// HBM 64 components at a time and expanded in registers to one byte per
-// component (int8 +-1, or fp8 e4m3 +-1.0 = 0x38 / 0xB8): a 4-bit group is
-// spread to the low bit of four bytes with one multiply and a mask, and
-// v_perm_b32 maps each 0/1 byte to the two encodings. The expanded stage
-// (2 x 256 rows x 64 bytes, rows padded to 80 bytes so 16 lanes of a
-// 16-byte LDS read touch 64 distinct banks) is double-buffered in LDS: while
-// the waves run MFMAs on stage s, every thread expands its row of stage s+1.
-// Packed bits are fetched one group of four stages ahead.
+// int8 engine (mfma_search_kernel): the packed bits of the 256 rows and 256
+// queries are read 64 components at a time and expanded once per workgroup
+// to int8 +-1 bytes (a 4-bit group is spread to four bytes with one multiply
+// and a mask, v_perm_b32 maps 0/1 bytes to +-1); the expanded stage (rows
+// padded to 80 bytes so 16 lanes of a 16-byte LDS read touch 64 distinct
+// banks) is double-buffered in LDS while the other buffer feeds the MFMAs.
+//
+// fp8 engine (mfma_direct_kernel): no LDS. Every lane loads the packed bits
+// of its own operand rows and expands them in registers right before the
+// matrix instructions, with one shift and one bit insert per 4 bytes; the
+// LDS variant of this engine spent as many LDS cycles on operand traffic as
+// matrix cycles.
 //
 // Epilogue per block: distance = (D - dot) / 2, masked by each query's own
 // window and the chunk end, folded into a per-lane 64-bit running minimum of
@@ -49,8 +52,6 @@ __device__ __forceinline__ void expand32(uint32_t w, uint32_t lut, uint32_t* o) 
     o[m] = __builtin_amdgcn_perm(0u, lut, spread);
   }
 }
-template <int FMT> struct Acc { typedef v16i T; };
-template <> struct Acc<1> { typedef v16f T; };
 
 template <int FMT, int WR, int WQ, int TR, int TQ>
 __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t words, int64_t nq, const uint32_t* __restrict__ q_hv,
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
 {
   constexpr int NTHR = 64 * WR * WQ, MR = WR * TR * 32, NQ = WQ * TQ * 32;
   constexpr int ROWS = MR + NQ, RPT = (ROWS + NTHR - 1) / NTHR;
-  typedef typename Acc<FMT>::T AccT;
+  static_assert(FMT == 0, "the LDS kernel is the int8 engine");
+  typedef v16i AccT;
   __shared__ __attribute__((aligned(16))) uint8_t sbuf[2][ROWS * LROW];
   const int64_t tile = blockIdx.x;
   const int64_t a64 = tlo[tile] + (int64_t)blockIdx.y * chunk;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
   const uint32_t a = (uint32_t)a64, b = (uint32_t)min(a64 + chunk, t_hi);
   const uint32_t D = words * 32;
   const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w % WR, wq = w / WR;
-  const uint32_t lut = FMT == 0 ? 0x0000FF01u : 0x0000B838u;
+  const uint32_t lut = 0x0000FF01u;  // byte 0 -> +1 (0x01), byte 1 -> -1 (0xFF)
 
   // expansion rows of this thread: row < MR is a library row of the block,
   // row >= MR is query row - MR of the tile
@@ -133,39 +135,20 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
   auto mfma_stage = [&](int buf, AccT (&acc)[TR][TQ]) {
     const uint8_t* A = sbuf[buf];
     const uint8_t* B = sbuf[buf] + MR * LROW;
-    if constexpr (FMT == 0) {
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        v4i av[TR], bv[TQ];
+    for (int ks = 0; ks < 2; ++ks) {
+      v4i av[TR], bv[TQ];
 #pragma unroll
-        for (int i = 0; i < TR; ++i)
-          av[i] = *(const v4i*)(A + (wr * TR * 32 + i * 32 + (l & 31)) * LROW + ks * 32 + 16 * (l >> 5));
+      for (int i = 0; i < TR; ++i)
+        av[i] = *(const v4i*)(A + (wr * TR * 32 + i * 32 + (l & 31)) * LROW + ks * 32 + 16 * (l >> 5));
 #pragma unroll
-        for (int j = 0; j < TQ; ++j)
-          bv[j] = *(const v4i*)(B + (wq * TQ * 32 + j * 32 + (l & 31)) * LROW + ks * 32 + 16 * (l >> 5));
+      for (int j = 0; j < TQ; ++j)
+        bv[j] = *(const v4i*)(B + (wq * TQ * 32 + j * 32 + (l & 31)) * LROW + ks * 32 + 16 * (l >> 5));
 #pragma unroll
-        for (int i = 0; i < TR; ++i)
-#pragma unroll
-          for (int j = 0; j < TQ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[i], bv[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      v8i bv[TQ];
-#pragma unroll
-      for (int j = 0; j < TQ; ++j) {
-        const v4i* pb_ = (const v4i*)(B + (wq * TQ * 32 + j * 32 + (l & 31)) * LROW + 32 * (l >> 5));
-        v4i y0 = pb_[0], y1 = pb_[1];
-        bv[j] = (v8i){y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-      }
-#pragma unroll
-      for (int i = 0; i < TR; ++i) {
-        const v4i* pa_ = (const v4i*)(A + (wr * TR * 32 + i * 32 + (l & 31)) * LROW + 32 * (l >> 5));
-        v4i x0 = pa_[0], x1 = pa_[1];
-        v8i av = (v8i){x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      for (int i = 0; i < TR; ++i)
 #pragma unroll
         for (int j = 0; j < TQ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], 0, 0, 0, 0, 0, 0);
-      }
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   };
 
@@ -228,6 +211,154 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
   }
 }
 
+// fp8 e4m3 +-1 bytes of 32 packed bits, for the register-direct kernel:
+// byte j of dword m carries bit (m + 8 j) (the sign bit of 0x38 = +1.0), so
+// each dword costs one shift and one and-or. The order of components inside
+// a k group differs from the packed order, but identically for both
+// operands, which leaves every dot product unchanged.
+// sel = 0x80808080 and one = 0x38383838 live in VGPRs: v_bfi_b32 takes no
+// literal operands, and with them each dword is one shift + one bit insert.
+__device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t one) {
+  v8i o;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const uint32_t x = w << (7 - m);
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(one));
+    o[m] = (int)r;
+  }
+  return o;
+}
+
+// Register-direct form of the fp8 search: no LDS and no barriers. Each lane
+// reads the packed bits of its own operand rows (16 bytes = 4 stages of 32
+// components per row and k half) from global memory one group ahead and
+// expands them in registers right before the matrix instructions. Within a
+// group of 256 components (8 words per row), k half h of every 32 x 32 x 64
+// step takes words 4h .. 4h + 3 of the group, stage s word 4h + s; A (library
+// rows) and B (queries) use the same assignment, so every dot product is the
+// full bipolar inner product. The four waves of a row half share library
+// rows and the two waves of a query quarter share query rows through L1.
+template <int WR, int WQ, int TR, int TQ>
+__global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_direct_kernel(uint32_t words, int64_t nq,
+    const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
+    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
+    const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
+    const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig, uint64_t* __restrict__ keys,
+    int64_t chunk)
+{
+  constexpr int MR = WR * TR * 32, NQ = WQ * TQ * 32;
+  const int64_t tile = blockIdx.x;
+  const int64_t a64 = tlo[tile] + (int64_t)blockIdx.y * chunk;
+  const int64_t t_hi = thi[tile];
+  if (a64 >= t_hi) return;
+  const uint32_t a = (uint32_t)a64, b = (uint32_t)min(a64 + chunk, t_hi);
+  const uint32_t D = words * 32;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w % WR, wq = w / WR;
+  const int h = l >> 5;
+
+  // query columns of this lane (B rows and epilogue columns coincide)
+  const uint32_t* qrow[TQ];
+  uint32_t qlo[TQ], qhi[TQ], qid[TQ];
+  uint64_t bk[TQ];
+  bool qok[TQ];
+#pragma unroll
+  for (int j = 0; j < TQ; ++j) {
+    const int64_t qs = tile * NQ + wq * TQ * 32 + j * 32 + (l & 31);
+    qok[j] = qs < nq;
+    qid[j] = qok[j] ? qperm[qs] : qperm[nq - 1];
+    qlo[j] = qok[j] ? (uint32_t)lo[qid[j]] : 0u;
+    qhi[j] = qok[j] ? (uint32_t)hi[qid[j]] : 0u;
+    qrow[j] = q_hv + (size_t)qid[j] * words + 4 * h;
+    bk[j] = ~0ull;
+  }
+  const uint32_t G = words / 8;
+  const uint32_t nblk = (b - a + MR - 1) / MR;
+  uint32_t sel = 0x80808080u, one = 0x38383838u;
+  asm volatile("" : "+v"(sel), "+v"(one));  // keep both in VGPRs
+
+  for (uint32_t blk = 0; blk < nblk; ++blk) {
+    const uint32_t* arow[TR];
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const uint32_t row = a + blk * MR + wr * TR * 32 + i * 32 + (l & 31);
+      arow[i] = lib + (size_t)min(row, b - 1u) * words + 4 * h;
+    }
+    v16f acc[TR][TQ];
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int j = 0; j < TQ; ++j) acc[i][j] = v16f{0};
+    // packed words of two groups in flight: x* is consumed while y* loads
+    uint4 xa[TR], xb[TQ], ya[TR], yb[TQ];
+    auto load = [&](uint32_t g, uint4 (&da)[TR], uint4 (&db)[TQ]) {
+      const uint32_t off = (g < G ? g : G - 1) * 8;
+#pragma unroll
+      for (int i = 0; i < TR; ++i) da[i] = *(const uint4*)(arow[i] + off);
+#pragma unroll
+      for (int j = 0; j < TQ; ++j) db[j] = *(const uint4*)(qrow[j] + off);
+      __builtin_amdgcn_sched_barrier(0);  // issued before the group's work
+    };
+    auto group = [&](const uint4 (&ca)[TR], const uint4 (&cb)[TQ]) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        v8i bv[TQ];
+#pragma unroll
+        for (int j = 0; j < TQ; ++j) {
+          const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
+          bv[j] = expand_pm1_fp8(x, sel, one);
+        }
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+          const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
+          const v8i av = expand_pm1_fp8(x, sel, one);
+#pragma unroll
+          for (int j = 0; j < TQ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], 0, 0,
+                                                                         0, 0, 0, 0);
+        }
+      }
+    };
+    load(0, xa, xb);
+    for (uint32_t g = 0; g < G; g += 2) {  // G = D / 256 is even
+      load(g + 1, ya, yb);
+      group(xa, xb);
+      load(g + 2, xa, xb);
+      group(ya, yb);
+    }
+    const uint32_t base = a + blk * MR + wr * TR * 32;
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg) {
+        const uint32_t g0 = base + i * 32 + 8 * rg + 4 * (l >> 5);
+        const uint4 o4 = *(const uint4*)(orig + g0);  // orig is padded past the end
+        const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const uint32_t g = g0 + r4;
+#pragma unroll
+          for (int j = 0; j < TQ; ++j) {
+            const int dot = (int)acc[i][j][4 * rg + r4];
+            const uint32_t d = (uint32_t)((int)D - dot) >> 1;
+            const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
+            const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;
+            bk[j] = key < bk[j] ? key : bk[j];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TQ; ++j) {
+    const uint64_t k = bk[j];
+    const uint64_t k2 = __shfl_xor(k, 32);
+    const uint64_t km = k < k2 ? k : k2;
+    if (l < 32 && qok[j] && km != ~0ull)
+      atomicMin((unsigned long long*)(keys + qid[j]), (unsigned long long)km);
+  }
+}
+
 constexpr int kMfWR = 2, kMfWQ = 4, kMfTR = 4, kMfTQ = 2;
 constexpr int kMfQueries = kMfWQ * kMfTQ * 32;  // 256 per workgroup
 constexpr int64_t kMfChunk = 4096;
@@ -252,7 +383,7 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
             kMfChunk);
     else
-        mfma_search_kernel<1, kMfWR, kMfWQ, kMfTR, kMfTQ><<<grid, block, 0, s>>>(
+        mfma_direct_kernel<kMfWR, kMfWQ, kMfTR, kMfTQ><<<grid, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
             kMfChunk);
     return hipGetLastError();

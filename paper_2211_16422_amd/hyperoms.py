@@ -96,7 +96,8 @@ _sig("homs_device_errors", [_P, ctypes.POINTER(ctypes.c_uint32), _P])
 class _Profile(ctypes.Structure):
     _fields_ = [("search_ms", ctypes.c_double), ("encode_ms", ctypes.c_double),
                 ("prep_ms", ctypes.c_double), ("search_launches", ctypes.c_int64),
-                ("encode_launches", ctypes.c_int64)]
+                ("encode_launches", ctypes.c_int64), ("score_ms", ctypes.c_double),
+                ("score_launches", ctypes.c_int64)]
 
 
 _sig("homs_profile_enable", [_P, _i32])
@@ -456,7 +457,8 @@ class Context:
         p = _Profile()
         self._ck(_lib.homs_profile_read(self._h, ctypes.byref(p)))
         return {"search_ms": p.search_ms, "encode_ms": p.encode_ms, "prep_ms": p.prep_ms,
-                "search_launches": p.search_launches, "encode_launches": p.encode_launches}
+                "search_launches": p.search_launches, "encode_launches": p.encode_launches,
+                "score_ms": p.score_ms, "score_launches": p.score_launches}
 
     def device_errors(self) -> int:
         f = ctypes.c_uint32(0)
