@@ -228,6 +228,9 @@ homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv
  *  narrow_group  narrow queries per work item, a multiple of 4 (>= 4).
  *  grid          workgroups of the persistent kernel (1..65535).
  *  bucket_da     precursor bucket width (Da) used to order queries into tiles.
+ *  engine        how wide tiles are scored: HOMS_ENGINE_POPCOUNT or
+ *                HOMS_ENGINE_MFMA_F8 (the default; both exact, see
+ *                homs_search_window).
  */
 typedef struct homs_batched_config {
     uint32_t narrow_max;
@@ -235,6 +238,7 @@ typedef struct homs_batched_config {
     uint32_t narrow_group;
     uint32_t grid;
     double bucket_da;
+    int32_t engine;
 } homs_batched_config;
 homs_status homs_batched_config_get(const homs_ctx *ctx, homs_batched_config *out);
 homs_status homs_batched_config_set(homs_ctx *ctx, const homs_batched_config *cfg);
@@ -260,8 +264,8 @@ homs_status homs_search_batched(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_h
 
 /*
  * Autotuner of the batched search: times candidate configurations on the
- * given batch (coordinate descent over chunk_rows, grid, narrow_max and
- * narrow_group from the current configuration, `reps` timed runs each after
+ * given batch (coordinate descent over engine, chunk_rows, grid, narrow_max
+ * and narrow_group from the current configuration, `reps` timed runs each after
  * one warm-up), keeps the fastest in the context and returns it with its
  * time per batch in *best_ms. The outputs hold the last run's (identical)
  * results. Synchronous.

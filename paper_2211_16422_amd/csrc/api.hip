@@ -606,6 +606,10 @@ bool batched_config_valid(const homs_batched_config* b, std::string* why)
         *why = "bucket_da must be finite and > 0";
         return false;
     }
+    if (b->engine != HOMS_ENGINE_POPCOUNT && b->engine != HOMS_ENGINE_MFMA_F8) {
+        *why = "engine must be HOMS_ENGINE_POPCOUNT or HOMS_ENGINE_MFMA_F8";
+        return false;
+    }
     return true;
 }
 
@@ -617,6 +621,7 @@ homs::BatchedConfig to_internal(const homs_batched_config& b)
     c.narrow_group = b.narrow_group;
     c.grid = b.grid;
     c.bucket_da = b.bucket_da;
+    c.engine = b.engine;
     return c;
 }
 
@@ -628,6 +633,7 @@ homs_batched_config to_public(const homs::BatchedConfig& c)
     b.narrow_group = c.narrow_group;
     b.grid = c.grid;
     b.bucket_da = c.bucket_da;
+    b.engine = c.engine;
     return b;
 }
 
@@ -670,7 +676,7 @@ homs_status run_batched(homs_ctx* c, const homs::BatchedConfig& cfg, int64_t nq,
             (uintptr_t)out_idx,   (uintptr_t)out_dist,   (uintptr_t)c->ws.ptr,
             (uintptr_t)c->lib.hv, (uintptr_t)c->lib.n,   (uintptr_t)cfg.narrow_max,
             (uintptr_t)cfg.chunk_rows, (uintptr_t)cfg.narrow_group, (uintptr_t)cfg.grid,
-            (uintptr_t)(cfg.bucket_da * 1e9)};
+            (uintptr_t)(cfg.bucket_da * 1e9), (uintptr_t)cfg.engine};
         if (!c->graph.exec || c->graph.key != key) {
             drop_graph(c);
             if (!c->capture_stream)
@@ -784,6 +790,7 @@ homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_h
     const uint32_t grids[] = {512, 1024, 2048, 4096};
     const uint32_t narrows[] = {256, 1024, 4096};
     const uint32_t groups[] = {16, 32, 64};
+    const uint32_t engines[] = {HOMS_ENGINE_POPCOUNT, HOMS_ENGINE_MFMA_F8};
     auto sweep = [&](auto set, const uint32_t* vals, int n) {
         for (int i = 0; i < n && st == HOMS_OK; ++i) {
             homs::BatchedConfig cand = cur;
@@ -796,6 +803,7 @@ homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_h
             }
         }
     };
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.engine = (int32_t)v; }, engines, 2);
     sweep([](homs::BatchedConfig& b, uint32_t v) { b.chunk_rows = v; }, chunks, 4);
     sweep([](homs::BatchedConfig& b, uint32_t v) { b.grid = v; }, grids, 4);
     sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_max = v; }, narrows, 3);

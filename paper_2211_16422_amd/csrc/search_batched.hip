@@ -17,6 +17,7 @@
 //   window bounds -> bucket histogram -> scan -> scatter (counting sort by
 //   (wide/narrow, charge, precursor bucket)) -> plan -> reset keys ->
 //   persistent search -> finalize.
+#include "mfma_direct.h"
 #include "popcount_tile.h"
 
 namespace homs {
@@ -236,18 +237,25 @@ __device__ __forceinline__ void narrow_query(uint32_t words, uint32_t qi,
         atomicMin(reinterpret_cast<unsigned long long*>(keys + qi), (unsigned long long)best);
 }
 
-__global__ __launch_bounds__(popc::kTile) void persistent_search_kernel(
-    uint32_t words, const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ order,
-    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t nq,
-    const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
-    const uint32_t* __restrict__ tile_item, int64_t max_tiles, uint32_t chunk_rows,
-    uint32_t narrow_group, Plan* __restrict__ plan, const uint32_t* __restrict__ lib_hv,
-    const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
+// ENGINE 0: popcount tiles, 256 threads; ENGINE 2: fp8 matrix-core tiles
+// (mfd::tile_rows), 512 threads. Narrow queries are spread over the waves.
+template <int ENGINE>
+__global__ __launch_bounds__(ENGINE == 0 ? popc::kTile : mfd::kThreads) void
+persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
+                         const uint32_t* __restrict__ order, const int64_t* __restrict__ lo,
+                         const int64_t* __restrict__ hi, int64_t nq,
+                         const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
+                         const uint32_t* __restrict__ tile_item, int64_t max_tiles,
+                         uint32_t chunk_rows, uint32_t narrow_group, Plan* __restrict__ plan,
+                         const uint32_t* __restrict__ lib_hv,
+                         const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
 {
+    static_assert(popc::kTile == mfd::kQueries, "both engines use 256-query tiles");
     __shared__ uint32_t s_item;
     const uint32_t n_wide = plan->n_wide;
     const uint32_t wide_items = plan->wide_items;
     const uint32_t total = plan->total_items;
+    const uint32_t waves = blockDim.x >> 6;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&plan->next_item, 1u);
         __syncthreads();
@@ -267,17 +275,18 @@ __global__ __launch_bounds__(popc::kTile) void persistent_search_kernel(
             const int64_t tile = l;
             const int64_t a = tile_lo[tile] + (int64_t)(item - tile_item[tile]) * chunk_rows;
             const int64_t b = min(a + (int64_t)chunk_rows, tile_hi[tile]);
-            if (a < b)
-                popc::popcount_tile_rows(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
-                                         (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
+            if (a < b) {
+                if constexpr (ENGINE == 0)
+                    popc::popcount_tile_rows(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
+                                             (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
+                else
+                    mfd::tile_rows(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
+                                   (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
+            }
         } else {
-            const uint32_t g = item - wide_items;
-            const uint32_t wave = threadIdx.x >> 6;
-            const uint32_t per_wave = narrow_group / (popc::kTile / 64);
-            const int64_t first = (int64_t)n_wide + (int64_t)g * narrow_group + wave * per_wave;
-            for (uint32_t k = 0; k < per_wave; ++k) {
-                const int64_t p = first + k;
-                if (p >= nq) break;
+            const int64_t first = (int64_t)n_wide + (int64_t)(item - wide_items) * narrow_group;
+            const int64_t last = min(first + (int64_t)narrow_group, nq);
+            for (int64_t p = first + (threadIdx.x >> 6); p < last; p += waves) {
                 const uint32_t qi = order[p];
                 if (hi[qi] > lo[qi])
                     narrow_query(words, qi, q_hv, (uint32_t)lo[qi], (uint32_t)hi[qi], lib_hv,
@@ -345,9 +354,14 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
     plan_kernel<<<1, 1024, 0, s>>>(nq, hist, order, lo, hi, cfg.chunk_rows, cfg.narrow_group,
                                    max_tiles, tile_lo, tile_hi, tile_item, plan);
     fill_u64_kernel<<<blocks_for(nq), kThreads, 0, s>>>(keys, nq, ~0ull);
-    persistent_search_kernel<<<cfg.grid, popc::kTile, 0, s>>>(
-        c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles, cfg.chunk_rows,
-        cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
+    if (cfg.engine == HOMS_ENGINE_MFMA_F8)
+        persistent_search_kernel<HOMS_ENGINE_MFMA_F8><<<cfg.grid, mfd::kThreads, 0, s>>>(
+            c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
+    else
+        persistent_search_kernel<HOMS_ENGINE_POPCOUNT><<<cfg.grid, popc::kTile, 0, s>>>(
+            c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(nq, keys, out_idx, out_dist, s);

@@ -32,6 +32,7 @@
 // (distance << 32 | library index); lanes l and l+32 hold the same query
 // columns and are merged with a shuffle before one atomicMin per query.
 #include "internal.h"
+#include "mfma_direct.h"
 
 namespace homs {
 namespace {
@@ -211,152 +212,19 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
   }
 }
 
-// fp8 e4m3 +-1 bytes of 32 packed bits, for the register-direct kernel:
-// byte j of dword m carries bit (m + 8 j) (the sign bit of 0x38 = +1.0), so
-// each dword costs one shift and one and-or. The order of components inside
-// a k group differs from the packed order, but identically for both
-// operands, which leaves every dot product unchanged.
-// sel = 0x80808080 and one = 0x38383838 live in VGPRs: v_bfi_b32 takes no
-// literal operands, and with them each dword is one shift + one bit insert.
-__device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t one) {
-  v8i o;
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const uint32_t x = w << (7 - m);
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(one));
-    o[m] = (int)r;
-  }
-  return o;
-}
-
-// Register-direct form of the fp8 search: no LDS and no barriers. Each lane
-// reads the packed bits of its own operand rows (16 bytes = 4 stages of 32
-// components per row and k half) from global memory one group ahead and
-// expands them in registers right before the matrix instructions. Within a
-// group of 256 components (8 words per row), k half h of every 32 x 32 x 64
-// step takes words 4h .. 4h + 3 of the group, stage s word 4h + s; A (library
-// rows) and B (queries) use the same assignment, so every dot product is the
-// full bipolar inner product. The four waves of a row half share library
-// rows and the two waves of a query quarter share query rows through L1.
-template <int WR, int WQ, int TR, int TQ>
-__global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_direct_kernel(uint32_t words, int64_t nq,
+__global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
     const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig, uint64_t* __restrict__ keys,
     int64_t chunk)
 {
-  constexpr int MR = WR * TR * 32, NQ = WQ * TQ * 32;
   const int64_t tile = blockIdx.x;
   const int64_t a64 = tlo[tile] + (int64_t)blockIdx.y * chunk;
   const int64_t t_hi = thi[tile];
   if (a64 >= t_hi) return;
-  const uint32_t a = (uint32_t)a64, b = (uint32_t)min(a64 + chunk, t_hi);
-  const uint32_t D = words * 32;
-  const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w % WR, wq = w / WR;
-  const int h = l >> 5;
-
-  // query columns of this lane (B rows and epilogue columns coincide)
-  const uint32_t* qrow[TQ];
-  uint32_t qlo[TQ], qhi[TQ], qid[TQ];
-  uint64_t bk[TQ];
-  bool qok[TQ];
-#pragma unroll
-  for (int j = 0; j < TQ; ++j) {
-    const int64_t qs = tile * NQ + wq * TQ * 32 + j * 32 + (l & 31);
-    qok[j] = qs < nq;
-    qid[j] = qok[j] ? qperm[qs] : qperm[nq - 1];
-    qlo[j] = qok[j] ? (uint32_t)lo[qid[j]] : 0u;
-    qhi[j] = qok[j] ? (uint32_t)hi[qid[j]] : 0u;
-    qrow[j] = q_hv + (size_t)qid[j] * words + 4 * h;
-    bk[j] = ~0ull;
-  }
-  const uint32_t G = words / 8;
-  const uint32_t nblk = (b - a + MR - 1) / MR;
-  uint32_t sel = 0x80808080u, one = 0x38383838u;
-  asm volatile("" : "+v"(sel), "+v"(one));  // keep both in VGPRs
-
-  for (uint32_t blk = 0; blk < nblk; ++blk) {
-    const uint32_t* arow[TR];
-#pragma unroll
-    for (int i = 0; i < TR; ++i) {
-      const uint32_t row = a + blk * MR + wr * TR * 32 + i * 32 + (l & 31);
-      arow[i] = lib + (size_t)min(row, b - 1u) * words + 4 * h;
-    }
-    v16f acc[TR][TQ];
-#pragma unroll
-    for (int i = 0; i < TR; ++i)
-#pragma unroll
-      for (int j = 0; j < TQ; ++j) acc[i][j] = v16f{0};
-    // packed words of two groups in flight: x* is consumed while y* loads
-    uint4 xa[TR], xb[TQ], ya[TR], yb[TQ];
-    auto load = [&](uint32_t g, uint4 (&da)[TR], uint4 (&db)[TQ]) {
-      const uint32_t off = (g < G ? g : G - 1) * 8;
-#pragma unroll
-      for (int i = 0; i < TR; ++i) da[i] = *(const uint4*)(arow[i] + off);
-#pragma unroll
-      for (int j = 0; j < TQ; ++j) db[j] = *(const uint4*)(qrow[j] + off);
-      __builtin_amdgcn_sched_barrier(0);  // issued before the group's work
-    };
-    auto group = [&](const uint4 (&ca)[TR], const uint4 (&cb)[TQ]) {
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        v8i bv[TQ];
-#pragma unroll
-        for (int j = 0; j < TQ; ++j) {
-          const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
-          bv[j] = expand_pm1_fp8(x, sel, one);
-        }
-#pragma unroll
-        for (int i = 0; i < TR; ++i) {
-          const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
-          const v8i av = expand_pm1_fp8(x, sel, one);
-#pragma unroll
-          for (int j = 0; j < TQ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], 0, 0,
-                                                                         0, 0, 0, 0);
-        }
-      }
-    };
-    load(0, xa, xb);
-    for (uint32_t g = 0; g < G; g += 2) {  // G = D / 256 is even
-      load(g + 1, ya, yb);
-      group(xa, xb);
-      load(g + 2, xa, xb);
-      group(ya, yb);
-    }
-    const uint32_t base = a + blk * MR + wr * TR * 32;
-#pragma unroll
-    for (int i = 0; i < TR; ++i) {
-#pragma unroll
-      for (int rg = 0; rg < 4; ++rg) {
-        const uint32_t g0 = base + i * 32 + 8 * rg + 4 * (l >> 5);
-        const uint4 o4 = *(const uint4*)(orig + g0);  // orig is padded past the end
-        const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const uint32_t g = g0 + r4;
-#pragma unroll
-          for (int j = 0; j < TQ; ++j) {
-            const int dot = (int)acc[i][j][4 * rg + r4];
-            const uint32_t d = (uint32_t)((int)D - dot) >> 1;
-            const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
-            const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;
-            bk[j] = key < bk[j] ? key : bk[j];
-          }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < TQ; ++j) {
-    const uint64_t k = bk[j];
-    const uint64_t k2 = __shfl_xor(k, 32);
-    const uint64_t km = k < k2 ? k : k2;
-    if (l < 32 && qok[j] && km != ~0ull)
-      atomicMin((unsigned long long*)(keys + qid[j]), (unsigned long long)km);
-  }
+  mfd::tile_rows(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64,
+                 (uint32_t)min(a64 + chunk, t_hi), lib, orig, keys);
 }
 
 constexpr int kMfWR = 2, kMfWQ = 4, kMfTR = 4, kMfTQ = 2;
@@ -383,7 +251,7 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
             kMfChunk);
     else
-        mfma_direct_kernel<kMfWR, kMfWQ, kMfTR, kMfTQ><<<grid, block, 0, s>>>(
+        mfma_direct_kernel<<<grid, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
             kMfChunk);
     return hipGetLastError();

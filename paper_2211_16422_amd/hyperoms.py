@@ -107,7 +107,7 @@ _sig("homs_profile_read", [_P, ctypes.POINTER(_Profile)])
 class _BatchedConfig(ctypes.Structure):
     _fields_ = [("narrow_max", ctypes.c_uint32), ("chunk_rows", ctypes.c_uint32),
                 ("narrow_group", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("bucket_da", ctypes.c_double)]
+                ("bucket_da", ctypes.c_double), ("engine", ctypes.c_int32)]
 
 
 _sig("homs_batched_config_get", [_P, ctypes.POINTER(_BatchedConfig)])

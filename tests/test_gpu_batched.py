@@ -68,13 +68,23 @@ def test_mixed_windows_have_both_classes(mixed):
     assert narrow.max() < 64 and wide.min() > 64 and set(np.unique(g.queries.charge)) == {2, 3, 4}
 
 
+ENGINES = [0, 2]  # wide tiles by popcount, by fp8 matrix cores
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_batched_matches_oracle(mixed, use_graph):
+def test_batched_matches_oracle(mixed, use_graph, engine):
     g = mixed.g
-    q_hv, o_idx, o_dist = mixed.queries(g.queries, g.tol_kind, g.tol_value)
-    idx, dist = mixed.ctx.search_batched(q_hv, _dev(g.queries.pmz), _dev(g.queries.charge),
-                                         _dev(g.tol_kind), _dev(g.tol_value), use_graph=use_graph)
-    _check(idx, dist, o_idx, o_dist)
+    before = mixed.ctx.batched_config()
+    try:
+        mixed.ctx.set_batched_config(engine=engine)
+        q_hv, o_idx, o_dist = mixed.queries(g.queries, g.tol_kind, g.tol_value)
+        idx, dist = mixed.ctx.search_batched(q_hv, _dev(g.queries.pmz), _dev(g.queries.charge),
+                                             _dev(g.tol_kind), _dev(g.tol_value),
+                                             use_graph=use_graph)
+        _check(idx, dist, o_idx, o_dist)
+    finally:
+        mixed.ctx.set_batched_config(**before)
 
 
 @pytest.mark.parametrize("cfg", [
@@ -84,11 +94,12 @@ def test_batched_matches_oracle(mixed, use_graph):
     dict(grid=1, narrow_group=4),            # one persistent workgroup drains the queue
     dict(bucket_da=1e-3, chunk_rows=100000),
 ])
-def test_batched_configurations(mixed, cfg):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_batched_configurations(mixed, cfg, engine):
     g = mixed.g
     before = mixed.ctx.batched_config()
     try:
-        mixed.ctx.set_batched_config(**cfg)
+        mixed.ctx.set_batched_config(engine=engine, **cfg)
         q_hv, o_idx, o_dist = mixed.queries(g.queries, g.tol_kind, g.tol_value)
         idx, dist = mixed.ctx.search_batched(q_hv, _dev(g.queries.pmz), _dev(g.queries.charge),
                                              _dev(g.tol_kind), _dev(g.tol_value),
