@@ -486,18 +486,18 @@ class Model:
     def __init__(self, ctx: Context, weights: dict):
         self.ctx = ctx
         self.hidden, self.dim = weights["W1"].shape
-        self.embed = weights["W2"].shape[0]
+        self.embed_dim = weights["W2"].shape[0]
         if self.dim != ctx.params.dim:
             raise ValueError("W1 must be [hidden, D]")
         w = self._host(weights)
         h = _P()
-        ctx._ck(_lib.homs_model_create(ctx._h, self.hidden, self.embed,
+        ctx._ck(_lib.homs_model_create(ctx._h, self.hidden, self.embed_dim,
                                        *[_np_ptr(w[k]) for k in WEIGHT_NAMES], ctypes.byref(h)))
         self._h = h
 
     def _host(self, weights):
         shapes = {"W1": (self.hidden, self.dim), "b1": (self.hidden,),
-                  "W2": (self.embed, self.hidden), "b2": (self.embed,)}
+                  "W2": (self.embed_dim, self.hidden), "b2": (self.embed_dim,)}
         out = {}
         for k in WEIGHT_NAMES:
             a = np.ascontiguousarray(weights[k], dtype=np.float32)
@@ -524,8 +524,8 @@ class Model:
     def get_weights(self) -> dict:
         w = {"W1": np.zeros((self.hidden, self.dim), np.float32),
              "b1": np.zeros(self.hidden, np.float32),
-             "W2": np.zeros((self.embed, self.hidden), np.float32),
-             "b2": np.zeros(self.embed, np.float32)}
+             "W2": np.zeros((self.embed_dim, self.hidden), np.float32),
+             "b2": np.zeros(self.embed_dim, np.float32)}
         self.ctx._ck(_lib.homs_model_get_weights(self._h, *[_np_ptr(w[k]) for k in WEIGHT_NAMES]))
         return w
 
@@ -535,7 +535,7 @@ class Model:
         dev = self.ctx.device
         n = hv.shape[0]
         if out is None:
-            out = torch.empty((n, self.embed), dtype=torch.float32, device=dev)
+            out = torch.empty((n, self.embed_dim), dtype=torch.float32, device=dev)
         self.ctx._ck(_lib.homs_model_embed(self._h, n, _dptr(hv, torch.int32, "hv", dev),
                                            _dptr(out, torch.float32, "out", dev), _stream(dev)))
         return out
@@ -546,8 +546,8 @@ class Model:
         dev = self.ctx.device
         g = {"W1": np.zeros((self.hidden, self.dim), np.float32),
              "b1": np.zeros(self.hidden, np.float32),
-             "W2": np.zeros((self.embed, self.hidden), np.float32),
-             "b2": np.zeros(self.embed, np.float32)}
+             "W2": np.zeros((self.embed_dim, self.hidden), np.float32),
+             "b2": np.zeros(self.embed_dim, np.float32)}
         loss = ctypes.c_float(0.0)
         self.ctx._ck(_lib.homs_model_gradients(
             self._h, q_hv.shape[0], _dptr(q_hv, torch.int32, "q_hv", dev),
