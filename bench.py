@@ -212,7 +212,8 @@ def main():
                 "unit": "TFLOP/s" if name == "mfma_fp8" else "TOP/s",
                 "frac": round(ach / MFMA_PEAK_TOPS, 4), "traffic": traffic,
                 "peak_kind": f"dense {fmt} matrix peak of MI355X",
-                "kernel": f"mfma_search_kernel<{fmt}>", "kernel_ms": round(kernel_ms, 3),
+                "kernel": ("mfma_direct_kernel (fp8 e4m3)" if name == "mfma_fp8" else
+                           "mfma_search_kernel (int8)"), "kernel_ms": round(kernel_ms, 3),
                 "ops_per_pair": 2 * w.dim}
 
     search_ms = prof["search_ms"] / max(prof["search_launches"], 1)

@@ -7,13 +7,14 @@
 //
 // Selecting k of up to a few million scores per query is done in one scoring
 // pass over the window:
-//  1. threshold: score a regular sample of the window (every 2^j-th row of
-//     the sorted library, so that neighbouring queries share sample rows in
-//     cache) on the VALU and take the r-th largest sample score, r chosen so
-//     that about min(kTargetMul * k, kCapacity / 4) window candidates are
-//     expected at or above it (a quarter of the buffer, so overflow needs a
-//     sample four times off its expectation);
-//     windows of at most kSample candidates keep everything;
+//  1. threshold: per tile of 128 m/z-ordered queries, score a regular sample
+//     of the union of its windows (every 2^j-th sorted row, at most kSample
+//     rows) on matrix cores; per query take the r-th largest of its in-window
+//     sample scores (radix select), r chosen so that about
+//     min(kTargetMul * k, kCapacity / 4) window candidates are expected at or
+//     above it (a quarter of the buffer, so overflow needs a sample four
+//     times off its expectation); windows of at most kSample candidates keep
+//     everything;
 //  2. collect: score every (query, candidate) pair on matrix cores (bf16
 //     operands, fp32 accumulation, 128 library rows x 128 m/z-ordered queries
 //     per workgroup) and append in-window pairs at or above the query's
@@ -44,7 +45,6 @@ constexpr int kThreads = 256;
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads); }
 
-__device__ __forceinline__ float bf(uint32_t v16) { return __uint_as_float(v16 << 16); }
 
 // order-preserving map of a float onto uint32 (larger float, larger key)
 __device__ __forceinline__ uint32_t fkey(float x)
@@ -90,50 +90,154 @@ __device__ void bitonic_desc(uint64_t* a, int n)
     }
 }
 
-// one workgroup per query (sorted position p): its sampled threshold
-__global__ __launch_bounds__(kThreads) void threshold_kernel(
-    int64_t nq, int E, int k, const uint16_t* __restrict__ q_sorted,
-    const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
-    const int64_t* __restrict__ hi, const uint16_t* __restrict__ lib_emb, float* __restrict__ thr)
+// Sample grid of a tile of 128 m/z-ordered queries: the rows g0 + m 2^sh
+// (m < n) of the sorted library inside the union of the tile's windows, with
+// the smallest sh that keeps n <= kSample (n = 0 when the union itself has at
+// most kSample rows, so no query of the tile needs a threshold).
+struct SampleGrid {
+    int64_t g0;
+    int32_t sh;
+    int32_t n;
+};
+
+// Scores of every query of a tile against its sample grid, on matrix cores
+// (same tiling as collect_kernel): S[q][m] = e_q . e_(row m), fp32.
+__global__ __launch_bounds__(256) void sample_scores_kernel(
+    int E, int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
+    const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
+    const uint16_t* __restrict__ lib_emb, SampleGrid* __restrict__ grids, float* __restrict__ S)
 {
-    __shared__ uint64_t s[kSample];
-    const int64_t p = blockIdx.x;
+    using namespace gemm;
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kTM * kRowBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[2][kTN * kRowBytes];
+    const int64_t tile = blockIdx.x;
+    const int64_t u0 = tile_lo[tile], u1 = tile_hi[tile];
+    SampleGrid gr{u0, 0, 0};
+    if (u1 - u0 > kSample) {
+        int sh = 1;
+        while (((u1 - u0 + ((int64_t)1 << sh) - 1) >> sh) > kSample) ++sh;
+        const int64_t st = (int64_t)1 << sh;
+        gr.g0 = (u0 + st - 1) & ~(st - 1);
+        gr.sh = sh;
+        gr.n = (int32_t)((u1 - gr.g0 + st - 1) >> sh);
+    }
+    if (threadIdx.x == 0) grids[tile] = gr;
+    if (gr.n == 0) return;  // uniform
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
+    const int64_t p0 = q_begin + tile * kTileQ;
+    const int64_t qlast = q_end - 1;
+    const int row0 = t >> 1, part0 = (t * 2) & 3;
+    const uint16_t* b_row = q_sorted + (size_t)min(p0 + row0, qlast) * E + part0 * 8;
+    uint8_t* sa_dst = &sA[0][0] + row0 * kRowBytes + part0 * 16;
+    uint8_t* sb_dst = &sB[0][0] + row0 * kRowBytes + part0 * 16;
+    float* Sq = S + (size_t)(tile * kTileQ) * kSample;
+    for (int m0 = 0; m0 < gr.n; m0 += kTM) {
+        const int64_t mrow = gr.g0 + ((int64_t)min(m0 + row0, gr.n - 1) << gr.sh);
+        const uint16_t* a_row = lib_emb + (size_t)mrow * E + part0 * 8;
+        Stage st;
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
+        const int nk = E / kTK;
+        st = load_stage(a_row, b_row, 0);
+        store_stage(st, sa_dst, sb_dst, 0);
+        __syncthreads();
+        for (int s = 0; s < nk; ++s) {
+            const int b = s & 1;
+            if (s + 1 < nk) st = load_stage(a_row, b_row, (s + 1) * kTK);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x8 av[2], bv[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    av[i] = *(const bf16x8*)(sA[b] + (wr * 64 + i * 32 + (l & 31)) * kRowBytes +
+                                             ks * 32 + 16 * (l >> 5));
+                    bv[i] = *(const bf16x8*)(sB[b] + (wn * 64 + i * 32 + (l & 31)) * kRowBytes +
+                                             ks * 32 + 16 * (l >> 5));
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j],
+                                                                           acc[i][j], 0, 0, 0);
+            }
+            if (s + 1 < nk) store_stage(st, sa_dst, sb_dst, b ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = wn * 64 + j * 32 + (l & 31);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int m = m0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                    if (m < gr.n) Sq[(size_t)q * kSample + m] = acc[i][j][r];
+                }
+        }
+    }
+}
+
+// One workgroup per query of the pass: the r-th largest of its in-window
+// sample scores (radix select over order-preserving keys, 8 bits per round),
+// with r chosen so that about min(kTargetMul k, kCapacity / 4) window
+// candidates are expected at or above it; -inf keeps the whole window.
+__global__ __launch_bounds__(kThreads) void threshold_kernel(
+    int64_t q_begin, int k, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    const int64_t* __restrict__ hi, const SampleGrid* __restrict__ grids,
+    const float* __restrict__ S, float* __restrict__ thr)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_digit, s_above;
+    const int64_t qp = blockIdx.x;  // position in the pass
+    const int64_t p = q_begin + qp;
     const uint32_t qi = qperm[p];
     const int64_t a = lo[qi], b = hi[qi], w = b - a;
-    if (w <= kSample) {  // the whole window is kept (uniform branch)
+    const SampleGrid gr = grids[qp / kTileQ];
+    int64_t i0 = 0, i1 = 0;
+    if (w > kSample && gr.n > 0) {
+        const int64_t st = (int64_t)1 << gr.sh;
+        i0 = a <= gr.g0 ? 0 : (a - gr.g0 + st - 1) >> gr.sh;
+        i1 = b <= gr.g0 ? 0 : min((int64_t)gr.n, (b - gr.g0 + st - 1) >> gr.sh);
+    }
+    const int ns = (int)max((int64_t)0, i1 - i0);
+    if (ns == 0) {  // uniform
         if (threadIdx.x == 0) thr[p] = -INFINITY;
         return;
     }
-    int sh = 1;
-    while (((w + ((int64_t)1 << sh) - 1) >> sh) > kSample) ++sh;
-    const int64_t g0 = (a + ((int64_t)1 << sh) - 1) & ~(((int64_t)1 << sh) - 1);
-    const int ns = (int)((b - g0 + ((int64_t)1 << sh) - 1) >> sh);  // in [kSample/2, kSample]
-    int np = 1;
-    while (np < ns) np <<= 1;
-    const uint16_t* qe = q_sorted + (size_t)p * E;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        uint64_t key = 0;
-        if (i < ns) {
-            const uint16_t* re = lib_emb + (size_t)(g0 + ((int64_t)i << sh)) * E;
-            float acc = 0.f;
-            for (int j = 0; j < E; j += 8) {
-                const uint4 rv = *(const uint4*)(re + j);
-                const uint4 qv = *(const uint4*)(qe + j);
-                acc += bf(rv.x & 0xFFFFu) * bf(qv.x & 0xFFFFu) + bf(rv.x >> 16) * bf(qv.x >> 16);
-                acc += bf(rv.y & 0xFFFFu) * bf(qv.y & 0xFFFFu) + bf(rv.y >> 16) * bf(qv.y >> 16);
-                acc += bf(rv.z & 0xFFFFu) * bf(qv.z & 0xFFFFu) + bf(rv.z >> 16) * bf(qv.z >> 16);
-                acc += bf(rv.w & 0xFFFFu) * bf(qv.w & 0xFFFFu) + bf(rv.w >> 16) * bf(qv.w >> 16);
-            }
-            key = ((uint64_t)fkey(acc) << 32) | (uint32_t)i;
-        }
-        s[i] = key;
-    }
-    __syncthreads();
-    bitonic_desc(s, np);
+    const float* v = S + (size_t)qp * kSample + i0;
     const int64_t target = min((int64_t)kTargetMul * k, (int64_t)kCapacity / 4);
-    int64_t r = (target * ns + w - 1) / w;
-    r = r < 1 ? 1 : (r > ns ? ns : r);
-    if (threadIdx.x == 0) thr[p] = fkey_inv((uint32_t)(s[r - 1] >> 32));
+    int64_t r64 = (target * ns + w - 1) / w;
+    uint32_t r = (uint32_t)(r64 < 1 ? 1 : (r64 > ns ? ns : r64));
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            const uint32_t key = fkey(v[i]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t above = 0;
+            int d = 255;
+            for (; d > 0; --d) {
+                if (above + hist[d] >= r) break;
+                above += hist[d];
+            }
+            s_digit = (uint32_t)d;
+            s_above = above;
+        }
+        __syncthreads();
+        prefix |= s_digit << shift;
+        mask |= 255u << shift;
+        r -= s_above;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) thr[p] = fkey_inv(prefix);
 }
 
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
@@ -338,7 +442,7 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
     if (plan) *plan = pl;
     const int64_t tiles = pl.batch / kTileQ;
     return al(nq * E * 2) + al(nq * 4) + al(pl.batch * 4) + al(pl.batch * (int64_t)kCapacity * 8) +
-           2 * al(tiles * 8);
+           2 * al(tiles * 8) + al(tiles * sizeof(SampleGrid)) + al(pl.batch * (int64_t)kSample * 4);
 }
 
 hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
@@ -363,11 +467,13 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     int64_t* tlo = (int64_t*)p;
     p += al(tiles_max * 8);
     int64_t* thi = (int64_t*)p;
+    p += al(tiles_max * 8);
+    SampleGrid* grids = (SampleGrid*)p;
+    p += al(tiles_max * sizeof(SampleGrid));
+    float* S = (float*)p;
 
     permute_rows_kernel<<<blocks_for(nq * (E / 8)), kThreads, 0, s>>>(nq, E, qperm, q_emb,
                                                                      q_sorted);
-    threshold_kernel<<<(uint32_t)nq, kThreads, 0, s>>>(nq, E, k, q_sorted, qperm, lo, hi,
-                                                       m->lib_emb, thr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
@@ -378,6 +484,9 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
         e = launch_tile_bounds(nb, qperm + b0, lo, hi, kTileQ, tlo, thi, s);
         if (e != hipSuccess) return e;
+        sample_scores_kernel<<<(uint32_t)tiles, 256, 0, s>>>(E, b0, b1, q_sorted, tlo, thi,
+                                                             m->lib_emb, grids, S);
+        threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
         collect_kernel<<<dim3((uint32_t)tiles, (uint32_t)max_chunks), 256, 0, s>>>(
