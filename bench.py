@@ -89,9 +89,9 @@ def main():
     ap.add_argument("--n-train", type=int, default=None, help="learned: training queries")
     ap.add_argument("--k", type=int, default=64, help="learned: shortlist size")
     ap.add_argument("--epochs", type=int, default=2, help="learned: training epochs")
-    ap.add_argument("--batch", type=int, default=4096, help="learned: training pairs per step")
-    ap.add_argument("--lr", type=float, default=1e-3, help="learned: Adam learning rate")
-    ap.add_argument("--tau", type=float, default=0.05, help="learned: InfoNCE temperature")
+    ap.add_argument("--batch", type=int, default=1024, help="learned: training pairs per step")
+    ap.add_argument("--lr", type=float, default=3e-5, help="learned: Adam learning rate")
+    ap.add_argument("--tau", type=float, default=0.02, help="learned: InfoNCE temperature")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

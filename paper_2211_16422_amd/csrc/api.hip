@@ -1123,6 +1123,8 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     if (!m->lib_emb_valid || m->lib_emb_lib_gen != c->lib_gen || m->lib_emb_w_gen != m->weights_gen)
         return fail(c, HOMS_E_STATE, "library embeddings are missing or stale "
                                      "(call homs_model_embed_library)");
+    if (!homs::learned_search_supports(m->E))
+        return fail(c, HOMS_E_UNSUPPORTED, "the shortlist search takes embed = 64, 128 or 256");
     if (k < 1 || k > homs::learned_max_k())
         return fail(c, HOMS_E_INVALID,
                     "k must be in [1, " + std::to_string(homs::learned_max_k()) + "]");
@@ -1136,16 +1138,14 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     const int tile = homs::search_popcount_tile();
     homs::LearnedScratchPlan plan;
     const size_t base = search_scratch_bytes(nq, tile);
-    const size_t extra = 2 * al(nq * 8) + al(nq * (size_t)m->E * 2) +
+    const size_t extra = al(homs::fallback_scratch_bytes(nq)) + al(nq * (size_t)m->E * 2) +
                          (d_out_shortlist ? 0 : al(nq * (size_t)k * 8)) +
                          homs::learned_scratch_bytes(nq, m->E, &plan);
     if (homs_status st = ensure_workspace(c, base + extra, s)) return st;
     SearchScratch w = carve(c->ws.ptr, nq, tile);
     char* p = (char*)c->ws.ptr + base;
-    int64_t* lo2 = (int64_t*)p;
-    p += al(nq * 8);
-    int64_t* hi2 = (int64_t*)p;
-    p += al(nq * 8);
+    void* fb_scratch = p;
+    p += al(homs::fallback_scratch_bytes(nq));
     uint16_t* q_emb = (uint16_t*)p;
     p += al(nq * (size_t)m->E * 2);
     int64_t* shortlist = d_out_shortlist;
@@ -1178,14 +1178,9 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
                                            w.hi, k, w.keys, d_out_fallback, shortlist, hook, s),
             "shortlist kernels");
     // exhaustive pass over the windows of the queries that fell back
-    HIP_TRY(c, homs::launch_fallback_windows(nq, d_out_fallback, w.lo, w.hi, lo2, hi2, s),
-            "fallback windows kernel");
-    HIP_TRY(c, homs::launch_tile_bounds(nq, qperm, lo2, hi2, tile, w.tile_lo, w.tile_hi, s),
-            "tile bounds kernel");
-    homs::TilePlan tplan;
-    HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, lo2, hi2, w.tile_lo, w.tile_hi,
-                                            tplan, w.keys, s),
-            "fallback search kernel");
+    HIP_TRY(c, homs::launch_fallback_scan(c, nq, d_q_hv, d_out_fallback, w.lo, w.hi, fb_scratch,
+                                          w.keys, s),
+            "fallback search kernels");
     hipEvent_t e2 = prof_mark(c, s);
     HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");
     hipEvent_t e3 = prof_mark(c, s);

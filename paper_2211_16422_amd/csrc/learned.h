@@ -56,6 +56,7 @@ struct LearnedScratchPlan {
     int64_t batch;  // queries per collection pass
 };
 int learned_max_k();
+bool learned_search_supports(int embed);  // embedding sizes the search kernels take
 size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan);
 hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
                                  const LearnedScratchPlan& plan, int64_t nq,
@@ -63,9 +64,12 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
                                  const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
                                  int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
                                  const SpanHook& hook, hipStream_t s);
-// lo2/hi2 = the query's window where fallback[q] is set, else empty
-hipError_t launch_fallback_windows(int64_t nq, const uint8_t* fallback, const int64_t* lo,
-                                   const int64_t* hi, int64_t* lo2, int64_t* hi2, hipStream_t s);
+// exhaustive search of the windows of the queries with fallback[q] set,
+// merged into keys (scratch: fallback_scratch_bytes)
+size_t fallback_scratch_bytes(int64_t nq);
+hipError_t launch_fallback_scan(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                const uint8_t* fallback, const int64_t* lo, const int64_t* hi,
+                                void* scratch, uint64_t* keys, hipStream_t s);
 size_t embed_ws_bytes(const homs_model* m, int64_t rows);
 size_t train_ws_bytes(const homs_model* m, int B);
 

@@ -140,14 +140,37 @@ __global__ void normalize_backward_kernel(int64_t M, int E, const float* __restr
     }
 }
 
-// column sums of a [M][N] fp32 matrix
-__global__ void colsum_kernel(int M, int N, const float* __restrict__ a, float* __restrict__ out)
+// column sums of a [M][N] fp32 matrix in two deterministic passes: partial
+// sums of kColRows-row slabs (grid.y = slab), then the slabs in order
+constexpr int kColRows = 128;
+
+__global__ void colsum_partial_kernel(int M, int N, const float* __restrict__ a,
+                                      float* __restrict__ part)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int m0 = blockIdx.y * kColRows, m1 = min(m0 + kColRows, M);
+    float acc = 0.f;
+    for (int m = m0; m < m1; ++m) acc += a[(size_t)m * N + n];
+    part[(size_t)blockIdx.y * N + n] = acc;
+}
+
+__global__ void colsum_final_kernel(int P, int N, const float* __restrict__ part,
+                                    float* __restrict__ out)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float acc = 0.f;
-    for (int m = 0; m < M; ++m) acc += a[(size_t)m * N + n];
+    for (int p = 0; p < P; ++p) acc += part[(size_t)p * N + n];
     out[n] = acc;
+}
+
+inline void colsum(int M, int N, const float* a, float* part, float* out, hipStream_t s)
+{
+    const int P = (M + kColRows - 1) / kColRows;
+    colsum_partial_kernel<<<dim3((unsigned)((N + 255) / 256), (unsigned)P), 256, 0, s>>>(M, N, a,
+                                                                                         part);
+    colsum_final_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(P, N, part, out);
 }
 
 __global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __restrict__ g,
@@ -299,7 +322,8 @@ size_t train_ws_bytes(const homs_model* m, int B)
     return 2 * al(M2 * D * 2) + al(M2 * H * 4) + 2 * al(M2 * H * 2) + 3 * al(M2 * E * 4) +
            al(M2 * E * 2) + al(M2 * 4) + al(E * M2 * 2) + al((size_t)B * B * 4) +
            2 * al((size_t)B * B * 2) + al(M2 * E * 4) + al(M2 * E * 2) + al(E * M2 * 2) +
-           al(M2 * H * 4) + al(M2 * H * 2) + al(H * M2 * 2);
+           al(M2 * H * 4) + al(M2 * H * 2) + al(H * M2 * 2) +
+           al(((M2 + kColRows - 1) / kColRows) * std::max(H, E) * 4);
 }
 
 hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t* r_hv, float tau,
@@ -344,6 +368,7 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
     float* da1 = (float*)take((size_t)M2 * H * 4);
     uint16_t* da1b = (uint16_t*)take((size_t)M2 * H * 2);
     uint16_t* da1T = (uint16_t*)take((size_t)H * M2 * 2);
+    float* colpart = (float*)take((size_t)((M2 + kColRows - 1) / kColRows) * std::max(H, E) * 4);
 
     using namespace gemm;
     hipError_t err = hipSuccess;
@@ -374,7 +399,7 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
     STEP(gemm_nt<kStoreF32>(s, B, E, B, dST, B, eT, M2, 1.f / tau, nullptr, nullptr,
                             dE + (size_t)B * E, E, nullptr, 0));
     normalize_backward_kernel<<<(uint32_t)((M2 + 3) / 4), 256, 0, s>>>(M2, E, e, sc, dE, dz, dzb);
-    colsum_kernel<<<(uint32_t)((E + 255) / 256), 256, 0, s>>>(M2, E, dz, m->gb2);
+    colsum(M2, E, dz, colpart, m->gb2, s);
     transpose_bf16_kernel<<<dim3((E + 31) / 32, (M2 + 31) / 32), 256, 0, s>>>(M2, E, dzb, E, dzT,
                                                                                 M2);
     transpose_bf16_kernel<<<dim3((H + 31) / 32, (M2 + 31) / 32), 256, 0, s>>>(M2, H, hb, H, hT,
@@ -385,7 +410,7 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
     // da1 = (dz W2) * [a1 > 0]
     STEP(gemm_nt<kMask | kStoreF32 | kStoreBf16>(s, M2, H, E, dzb, E, m->W2Th, E, 1.f, nullptr,
                                                  a1, da1, H, da1b, H));
-    colsum_kernel<<<(uint32_t)((H + 255) / 256), 256, 0, s>>>(M2, H, da1, m->gb1);
+    colsum(M2, H, da1, colpart, m->gb1, s);
     transpose_bf16_kernel<<<dim3((H + 31) / 32, (M2 + 31) / 32), 256, 0, s>>>(M2, H, da1b, H,
                                                                                 da1T, M2);
     // dW1 = da1^T X

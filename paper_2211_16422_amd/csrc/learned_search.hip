@@ -26,11 +26,14 @@
 //     exhaustive fallback and gets no shortlist;
 //  4. rescore: one lane per shortlist entry computes the exact Hamming
 //     distance; the wave minimum of (distance << 32 | library index) is merged
-//     into the query's key.
+//     into the query's key;
+//  5. fallback: the flagged queries are listed on the device and their whole
+//     windows scanned, one wave per 512-row unit, into the same keys.
 #include <algorithm>
 
 #include "gemm_bf16.h"
 #include "learned.h"
+#include "popcount_tile.h"
 
 namespace homs {
 namespace {
@@ -42,6 +45,7 @@ constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 4096;  // library rows per collection workgroup
 constexpr int kThreads = 256;
+constexpr int64_t kFallbackRows = 512;   // window rows per wave in the exhaustive fallback
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads); }
 
@@ -242,8 +246,25 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
 // cores and appends every in-window pair at or above the query's threshold.
-__global__ __launch_bounds__(256) void collect_kernel(
-    int E, int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
+// The tile's query embeddings are the B operands of every step, so each wave
+// keeps its two 32-query columns in registers for the whole chunk (E / 16
+// operand registers of 16 bytes per column); library rows go through one LDS
+// buffer (rows padded by 16 bytes, so the 32 lanes of a column read distinct
+// banks), and the next block's rows are loaded into registers while the
+// current block is multiplied, a whole block of matrix work ahead of use.
+// The epilogue tests each of the lane's 64 pairs with one compare when the
+// wave's 64 rows lie inside the lane's windows. Hits are rare; a position is
+// skipped unless some lane of the wave hits (a scalar branch on the ballot),
+// and hits are appended to the wave's own LDS list at positions counted from
+// the ballot (no atomics), which the wave flushes to the per-query global
+// buffers when it is nearly full and at the end: the global atomics of a
+// flush are independent, so their latency overlaps instead of stalling every
+// hit.
+constexpr int kWaveList = 2048;  // LDS entries per wave
+
+template <int E>
+__global__ __launch_bounds__(256, 1) void collect_kernel(
+    int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
@@ -251,20 +272,30 @@ __global__ __launch_bounds__(256) void collect_kernel(
     uint32_t* __restrict__ count, uint64_t* __restrict__ buf)
 {
     using namespace gemm;
-    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kTM * kRowBytes];
-    __shared__ __attribute__((aligned(16))) uint8_t sB[2][kTN * kRowBytes];
+    constexpr int KS = E / 16;              // 32 x 32 x 16 steps
+    constexpr int RB = E * 2 + 16;          // LDS bytes per library row
+    constexpr int PIECES = E / 8;           // 16-byte pieces per row
+    constexpr int PPT = 128 * PIECES / 256; // pieces per thread per block
+    __shared__ __attribute__((aligned(16))) uint8_t sA[128 * RB];
+    __shared__ uint64_t s_key[4][kWaveList];
+    __shared__ uint8_t s_col[4][kWaveList];  // query of the entry within the tile
+    // Chunks are fixed row ranges of the sorted library (blockIdx.y), clipped
+    // to the tile's candidate range: the workgroups of all tiles that cover a
+    // chunk run together (x varies fastest) and read the same rows, which
+    // then come from L2 instead of HBM.
     const int64_t tile = blockIdx.x;
-    const int64_t t_hi = tile_hi[tile];
-    const int64_t c0 = tile_lo[tile] + (int64_t)blockIdx.y * kCollectChunk;
-    if (c0 >= t_hi) return;
-    const int64_t c1 = min(c0 + kCollectChunk, t_hi);
+    const int64_t r0 = (int64_t)blockIdx.y * kCollectChunk;
+    const int64_t c0 = max(r0, tile_lo[tile]);
+    const int64_t c1 = min(r0 + kCollectChunk, tile_hi[tile]);
+    if (c0 >= c1) return;
     const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
     const int64_t qlast = q_end - 1;
 
-    // the two query columns each lane owns in the epilogue
+    // the two query columns of this lane: epilogue state and B operands
     int64_t qlo[2], qhi[2], qslot[2];
     float qthr[2];
+    bf16x8 bq[2][KS];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int64_t p = p0 + wn * 64 + j * 32 + (l & 31);
@@ -277,66 +308,97 @@ __global__ __launch_bounds__(256) void collect_kernel(
             qhi[j] = hi[qi];
             qthr[j] = thr[p];
         }
+        const uint16_t* qrow = q_sorted + (size_t)min(p, qlast) * E + 8 * (l >> 5);
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) bq[j][kk] = *(const bf16x8*)(qrow + kk * 16);
     }
 
-    const int row0 = t >> 1, part0 = (t * 2) & 3;
-    const uint16_t* b_row = q_sorted + (size_t)min(p0 + row0, qlast) * E + part0 * 8;
-    uint8_t* sa_dst = &sA[0][0] + row0 * kRowBytes + part0 * 16;
-    uint8_t* sb_dst = &sB[0][0] + row0 * kRowBytes + part0 * 16;
-    for (int64_t m0 = c0; m0 < c1; m0 += kTM) {
-        const uint16_t* a_row = lib_emb + (size_t)min(m0 + row0, c1 - 1) * E + part0 * 8;
-        Stage st;
+    // the wave's LDS hit list and its flush to the per-query global buffers
+    uint32_t wcount = 0;  // wave-uniform
+    const int64_t qbase = tile * kTileQ;  // pass slot of the tile's first query
+    auto flush = [&]() {
+        for (uint32_t e = (uint32_t)l; e < wcount; e += 64) {
+            const int64_t qs = qbase + s_col[w][e];
+            const uint32_t slot = atomicAdd(count + qs, 1u);
+            if (slot < (uint32_t)kCapacity) buf[(size_t)qs * kCapacity + slot] = s_key[w][e];
+        }
+        wcount = 0;
+    };
+
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 stg[PPT];
+#pragma unroll
+    for (int x = 0; x < PPT; ++x) {
+        const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
+        stg[x] = *(const u32x4*)(lib_emb + (size_t)min(c0 + row, c1 - 1) * E + part * 8);
+    }
+    for (int64_t m0 = c0; m0 < c1; m0 += 128) {
+        __syncthreads();  // the previous block's readers are done with sA
+#pragma unroll
+        for (int x = 0; x < PPT; ++x) {
+            const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
+            *(u32x4*)(sA + row * RB + part * 16) = stg[x];
+        }
+        __syncthreads();
+        const int64_t mn = m0 + 128 < c1 ? m0 + 128 : m0;  // the last block reloads itself
+#pragma unroll
+        for (int x = 0; x < PPT; ++x) {
+            const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
+            stg[x] = *(const u32x4*)(lib_emb + (size_t)min(mn + row, c1 - 1) * E + part * 8);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the next block's loads go out first
         f32x16 acc[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
-        const int nk = E / kTK;
-        st = load_stage(a_row, b_row, 0);
-        store_stage(st, sa_dst, sb_dst, 0);
-        __syncthreads();
-        for (int s = 0; s < nk; ++s) {
-            const int b = s & 1;
-            if (s + 1 < nk) st = load_stage(a_row, b_row, (s + 1) * kTK);
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x8 av[2], bv[2];
+        for (int kk = 0; kk < KS; ++kk) {
+            bf16x8 av[2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    av[i] = *(const bf16x8*)(sA[b] + (wr * 64 + i * 32 + (l & 31)) * kRowBytes +
-                                             ks * 32 + 16 * (l >> 5));
-                    bv[i] = *(const bf16x8*)(sB[b] + (wn * 64 + i * 32 + (l & 31)) * kRowBytes +
-                                             ks * 32 + 16 * (l >> 5));
-                }
+            for (int i = 0; i < 2; ++i)
+                av[i] = *(const bf16x8*)(sA + (wr * 64 + i * 32 + (l & 31)) * RB + kk * 32 +
+                                         16 * (l >> 5));
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j],
-                                                                           acc[i][j], 0, 0, 0);
-            }
-            if (s + 1 < nk) store_stage(st, sa_dst, sb_dst, b ^ 1);
-            __syncthreads();
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bq[j][kk],
+                                                                       acc[i][j], 0, 0, 0);
         }
+        const int64_t w0 = m0 + wr * 64;  // first row of this wave's 64
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            if (qslot[j] < 0) continue;
+            const bool inside = w0 >= qlo[j] && w0 + 64 <= qhi[j] && w0 + 64 <= c1;
+            const uint8_t col = (uint8_t)(wn * 64 + j * 32 + (l & 31));
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int64_t g =
-                        m0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                    const int64_t g = w0 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
                     const float sc = acc[i][j][r];
-                    if (g < c1 && g >= qlo[j] && g < qhi[j] && sc >= qthr[j]) {
-                        const uint32_t slot = atomicAdd(count + qslot[j], 1u);
-                        if (slot < (uint32_t)kCapacity)
-                            buf[(size_t)qslot[j] * kCapacity + slot] =
-                                ((uint64_t)fkey(sc) << 32) | (uint64_t)(0xFFFFFFFFu - lib_orig[g]);
+                    const bool ok = sc >= qthr[j] &&
+                                    (inside || (g < c1 && g >= qlo[j] && g < qhi[j]));
+                    const uint64_t m = __ballot(ok);
+                    if (m != 0) {  // wave-uniform
+                        if (wcount + 64 > kWaveList) {
+                            flush();
+                        }
+                        if (ok) {
+                            const uint32_t pos =
+                                wcount + __builtin_amdgcn_mbcnt_hi(
+                                             (uint32_t)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            s_key[w][pos] = ((uint64_t)fkey(sc) << 32) |
+                                            (uint64_t)(0xFFFFFFFFu - lib_orig[g]);
+                            s_col[w][pos] = col;
+                        }
+                        wcount += (uint32_t)__popcll(m);
                     }
                 }
         }
     }
+    flush();
 }
 
 // one workgroup per query of the pass: the k largest keys of its buffer
@@ -408,16 +470,34 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(
         atomicMin((unsigned long long*)(keys + qi), (unsigned long long)best);
 }
 
-// windows of the exhaustive pass: a query's own window if it fell back, else empty
-__global__ void fallback_windows_kernel(int64_t nq, const uint8_t* __restrict__ fallback,
-                                        const int64_t* __restrict__ lo,
-                                        const int64_t* __restrict__ hi, int64_t* __restrict__ lo2,
-                                        int64_t* __restrict__ hi2)
+// list of the queries that fell back (order irrelevant: results merge by atomicMin)
+__global__ void fallback_compact_kernel(int64_t nq, const uint8_t* __restrict__ fallback,
+                                        uint32_t* __restrict__ list, uint32_t* __restrict__ count)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    lo2[q] = lo[q];
-    hi2[q] = fallback[q] ? hi[q] : lo[q];
+    if (q < nq && fallback[q]) list[atomicAdd(count, 1u)] = (uint32_t)q;
+}
+
+// Exhaustive pass over the windows of the listed queries: unit u = (list
+// entry u / max_units, rows [lo + (u % max_units) R, + R) of its window), one
+// wave per unit, grid-stride so that a fixed launch covers any count.
+__global__ __launch_bounds__(kThreads) void fallback_scan_kernel(
+    uint32_t words, const uint32_t* __restrict__ q_hv, const int64_t* __restrict__ lo,
+    const int64_t* __restrict__ hi, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ count, int64_t max_units, const uint32_t* __restrict__ lib_hv,
+    const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
+{
+    const int64_t total = (int64_t)*count * max_units;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < total;
+         u += waves) {
+        const uint32_t qi = list[u / max_units];
+        const int64_t a = lo[qi] + (u % max_units) * kFallbackRows;
+        const int64_t b = min(a + (int64_t)kFallbackRows, hi[qi]);
+        if (a < b)  // wave-uniform
+            popc::window_rows_wave(words, qi, q_hv, (uint32_t)a, (uint32_t)b, lib_hv, lib_orig,
+                                   keys);
+    }
 }
 
 __global__ void zero_u32_kernel(int64_t n, uint32_t* __restrict__ p)
@@ -431,6 +511,8 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 int learned_max_k() { return kCapacity / 8; }
+
+bool learned_search_supports(int E) { return E == 64 || E == 128 || E == 256; }
 
 size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
 {
@@ -454,6 +536,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
 {
     if (nq <= 0) return hipSuccess;
     const int E = m->E;
+    if (!learned_search_supports(E)) return hipErrorInvalidValue;
     const int64_t tiles_max = plan.batch / kTileQ;
     char* p = (char*)scratch;
     uint16_t* q_sorted = (uint16_t*)p;
@@ -489,8 +572,16 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
-        collect_kernel<<<dim3((uint32_t)tiles, (uint32_t)max_chunks), 256, 0, s>>>(
-            E, b0, b1, q_sorted, qperm, lo, hi, thr, tlo, thi, m->lib_emb, c->lib.orig, count, buf);
+        const dim3 cgrid((uint32_t)tiles, (uint32_t)max_chunks);
+        if (E == 256)
+            collect_kernel<256><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+                                                      thi, m->lib_emb, c->lib.orig, count, buf);
+        else if (E == 128)
+            collect_kernel<128><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+                                                      thi, m->lib_emb, c->lib.orig, count, buf);
+        else
+            collect_kernel<64><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+                                                     thi, m->lib_emb, c->lib.orig, count, buf);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
                                                           shortlist, fallback);
@@ -502,11 +593,20 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     return hipSuccess;
 }
 
-hipError_t launch_fallback_windows(int64_t nq, const uint8_t* fallback, const int64_t* lo,
-                                   const int64_t* hi, int64_t* lo2, int64_t* hi2, hipStream_t s)
+size_t fallback_scratch_bytes(int64_t nq) { return al(nq * 4) + al(4); }
+
+hipError_t launch_fallback_scan(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                const uint8_t* fallback, const int64_t* lo, const int64_t* hi,
+                                void* scratch, uint64_t* keys, hipStream_t s)
 {
-    if (nq <= 0) return hipSuccess;
-    fallback_windows_kernel<<<blocks_for(nq), kThreads, 0, s>>>(nq, fallback, lo, hi, lo2, hi2);
+    if (nq <= 0 || c->lib.n <= 0) return hipSuccess;
+    uint32_t* list = (uint32_t*)scratch;
+    uint32_t* count = (uint32_t*)((char*)scratch + al(nq * 4));
+    zero_u32_kernel<<<1, 64, 0, s>>>(1, count);
+    fallback_compact_kernel<<<blocks_for(nq), kThreads, 0, s>>>(nq, fallback, list, count);
+    const int64_t max_units = (c->lib.n + kFallbackRows - 1) / kFallbackRows;
+    fallback_scan_kernel<<<2048, kThreads, 0, s>>>(c->words, q_hv, lo, hi, list, count, max_units,
+                                                   c->lib.hv, c->lib.orig, keys);
     return hipGetLastError();
 }
 

@@ -187,56 +187,6 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     }
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-// one wave scores one narrow query: lane = candidate row, query words via
-// scalar loads, each lane's row words via 16-byte vector loads
-__device__ __forceinline__ void narrow_query(uint32_t words, uint32_t qi,
-                                             const uint32_t* __restrict__ q_hv,
-                                             uint32_t q_lo, uint32_t q_hi,
-                                             const uint32_t* __restrict__ lib_hv,
-                                             const uint32_t* __restrict__ lib_orig,
-                                             uint64_t* __restrict__ keys)
-{
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t* qrow = q_hv + (size_t)qi * words;
-    uint64_t best = ~0ull;
-    for (uint32_t base = q_lo; base < q_hi; base += 64) {
-        const uint32_t row = base + lane;
-        const uint32_t rr = min(row, q_hi - 1u);
-        const uint32_t* rp = lib_hv + (size_t)rr * words;
-        uint32_t acc = 0;
-        for (uint32_t c = 0; c < words; c += popc::kWords) {
-            const popc::Slice qs = popc::scalar_slice(qrow + c);
-            uint32_t rv[popc::kWords];
-#pragma unroll
-            for (int i = 0; i < popc::kWords; i += 4) {
-                const uint4 t = *reinterpret_cast<const uint4*>(rp + c + i);
-                rv[i] = t.x;
-                rv[i + 1] = t.y;
-                rv[i + 2] = t.z;
-                rv[i + 3] = t.w;
-            }
-#pragma unroll
-            for (int i = 0; i < popc::kWords; ++i) popc::xor_popcount_add(acc, qs.v[i], rv[i]);
-        }
-        const uint64_t key =
-            row < q_hi ? (((uint64_t)acc << 32) | (uint64_t)lib_orig[rr]) : ~0ull;
-        best = key < best ? key : best;
-    }
-    best = wave_min_u64(best);
-    if (lane == 0 && best != ~0ull)
-        atomicMin(reinterpret_cast<unsigned long long*>(keys + qi), (unsigned long long)best);
-}
-
 // ENGINE 0: popcount tiles, 256 threads; ENGINE 2: fp8 matrix-core tiles
 // (mfd::tile_rows), 512 threads. Narrow queries are spread over the waves.
 template <int ENGINE>
@@ -289,8 +239,8 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
             for (int64_t p = first + (threadIdx.x >> 6); p < last; p += waves) {
                 const uint32_t qi = order[p];
                 if (hi[qi] > lo[qi])
-                    narrow_query(words, qi, q_hv, (uint32_t)lo[qi], (uint32_t)hi[qi], lib_hv,
-                                 lib_orig, keys);
+                    popc::window_rows_wave(words, qi, q_hv, (uint32_t)lo[qi], (uint32_t)hi[qi],
+                                           lib_hv, lib_orig, keys);
             }
         }
     }

@@ -309,6 +309,25 @@ def test_sampled_threshold_windows():
             f = fb.astype(bool)
             assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
             assert (sl[f] == -1).all()
+        # Degenerate weights: every embedding is the same unit vector, every
+        # score ties, so each sampled window keeps all its candidates and a
+        # window above the buffer size (8,192) overflows: those queries must
+        # fall back to the exhaustive answer, the others keep a valid shortlist.
+        E, H = s.p["W2"].shape
+        flat = {"W1": np.zeros_like(s.p["W1"]), "b1": np.zeros_like(s.p["b1"]),
+                "W2": np.zeros_like(s.p["W2"]), "b2": np.ones(E, np.float32)}
+        s.model.set_weights(flat)
+        s.model.embed_library()
+        idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, 16, value=500.0,
+                                           shortlist=True)
+        idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
+        assert (cnt > 8192).any() and (cnt <= 8192).any()
+        assert np.array_equal(fb.astype(bool), cnt > 8192)
+        f = fb.astype(bool)
+        assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
+        El = np.ones((g.library.n, E)) / np.sqrt(E)
+        Eq = np.ones((g.queries.n, E)) / np.sqrt(E)
+        _check_shortlists(s, 16, 500.0, idx, dist, fb, sl, El, Eq)
     finally:
         s.close()
 
