@@ -10,11 +10,11 @@
 //  1. threshold: per tile of 128 m/z-ordered queries, score a regular sample
 //     of the union of its windows (every 2^j-th sorted row, at most kSample
 //     rows) on matrix cores; per query take the r-th largest of its in-window
-//     sample scores (radix select), r chosen so that about
-//     min(kTargetMul * k, kCapacity / 4) window candidates are expected at or
-//     above it (a quarter of the buffer, so overflow needs a sample four
-//     times off its expectation); windows of at most kSample candidates keep
-//     everything;
+//     sample scores (radix select), r chosen so that about kCapacity / 4
+//     window candidates are expected at or above it (a quarter of the
+//     buffer: with r of at least 8 on the largest windows, both overflow and
+//     keeping fewer than k are far in the tails); windows of at most kSample
+//     (= kCapacity) candidates keep everything;
 //  2. collect: score every (query, candidate) pair on matrix cores (bf16
 //     operands, fp32 accumulation, 128 library rows x 128 m/z-ordered queries
 //     per workgroup) and append in-window pairs at or above the query's
@@ -38,9 +38,7 @@
 namespace homs {
 namespace {
 
-constexpr int kSample = 4096;    // most sampled candidates per window
-constexpr int kTargetMul = 16;   // expected candidates at or above the threshold:
-                                 // min(16 k, kCapacity / 4)
+constexpr int kSample = 8192;    // most sampled candidates per window
 constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 4096;  // library rows per collection workgroup
@@ -187,10 +185,10 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
 
 // One workgroup per query of the pass: the r-th largest of its in-window
 // sample scores (radix select over order-preserving keys, 8 bits per round),
-// with r chosen so that about min(kTargetMul k, kCapacity / 4) window
-// candidates are expected at or above it; -inf keeps the whole window.
+// with r chosen so that about kCapacity / 4 window candidates are expected
+// at or above it; -inf keeps the whole window.
 __global__ __launch_bounds__(kThreads) void threshold_kernel(
-    int64_t q_begin, int k, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    int64_t q_begin, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const SampleGrid* __restrict__ grids,
     const float* __restrict__ S, float* __restrict__ thr)
 {
@@ -213,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
         return;
     }
     const float* v = S + (size_t)qp * kSample + i0;
-    const int64_t target = min((int64_t)kTargetMul * k, (int64_t)kCapacity / 4);
+    const int64_t target = kCapacity / 4;
     int64_t r64 = (target * ns + w - 1) / w;
     uint32_t r = (uint32_t)(r64 < 1 ? 1 : (r64 > ns ? ns : r64));
     uint32_t prefix = 0, mask = 0;
@@ -569,7 +567,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         if (e != hipSuccess) return e;
         sample_scores_kernel<<<(uint32_t)tiles, 256, 0, s>>>(E, b0, b1, q_sorted, tlo, thi,
                                                              m->lib_emb, grids, S);
-        threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi, grids, S, thr);
+        threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
         const dim3 cgrid((uint32_t)tiles, (uint32_t)max_chunks);

@@ -288,15 +288,15 @@ def test_stale_library_embeddings_are_refused(tiny_learned):
 
 
 def test_sampled_threshold_windows():
-    """Windows larger than the unsampled size (library of 40,000): the
+    """Windows larger than the unsampled size (library of 60,000): the
     threshold comes from a sample; queries that fall back must carry the
     exhaustive answer and every other shortlist must be a valid top-k."""
-    s = LearnedSetup(n_ref=20000, n_query=300, seed=4)
+    s = LearnedSetup(n_ref=30000, n_query=300, seed=4)
     try:
         g = s.g
         cnt = oracle.window_counts(g.library.pmz, g.library.charge, g.queries.pmz,
                                    g.queries.charge, 0, 500.0)
-        assert (cnt > 4096).mean() > 0.5  # most windows take the sampled path
+        assert (cnt > 8192).mean() > 0.5  # most windows take the sampled path
         for k in (16, 64):
             idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k, value=500.0,
                                                shortlist=True)
@@ -318,16 +318,23 @@ def test_sampled_threshold_windows():
                 "W2": np.zeros_like(s.p["W2"]), "b2": np.ones(E, np.float32)}
         s.model.set_weights(flat)
         s.model.embed_library()
-        idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, 16, value=500.0,
-                                           shortlist=True)
-        idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
-        assert (cnt > 8192).any() and (cnt <= 8192).any()
-        assert np.array_equal(fb.astype(bool), cnt > 8192)
-        f = fb.astype(bool)
-        assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
         El = np.ones((g.library.n, E)) / np.sqrt(E)
         Eq = np.ones((g.queries.n, E)) / np.sqrt(E)
-        _check_shortlists(s, 16, 500.0, idx, dist, fb, sl, El, Eq)
+        seen = set()
+        for tol in (500.0, 150.0):
+            cnt = oracle.window_counts(g.library.pmz, g.library.charge, g.queries.pmz,
+                                       g.queries.charge, 0, tol)
+            seen |= set((cnt > 8192).tolist())
+            o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge,
+                                          s.o_q, g.queries.pmz, g.queries.charge, 0, tol)
+            idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, 16, value=tol,
+                                               shortlist=True)
+            idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
+            assert np.array_equal(fb.astype(bool), cnt > 8192)
+            f = fb.astype(bool)
+            assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
+            _check_shortlists(s, 16, tol, idx, dist, fb, sl, El, Eq)
+        assert seen == {True, False}  # both kinds of window were exercised
     finally:
         s.close()
 
