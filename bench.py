@@ -42,12 +42,14 @@ MFMA_PEAK_TOPS = 5000.0  # dense fp8 / int8 matrix peak of MI355X, TFLOP/s (TOP/
 
 # HBM bytes per launch of each search kernel on the default large workload,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
-# (profiles/search_popcount_large.md). Keyed by engine and the hash of the
+# (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
-MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12}
+MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
+                    ("mfma_fp8", "4bb9ca345dad1002"): 8.123e11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
-                  "mfma_fp8": ("search_mfma.hip",), "mfma_int8": ("search_mfma.hip",)}
+                  "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
+                  "mfma_int8": ("search_mfma.hip",)}
 
 
 VALU_PEAK_TOPS = VALU_MODEL_TOPS  # replaced by the live measurement in main()

@@ -393,7 +393,8 @@ homs_status homs_model_embed_library(homs_model *model, void *stream);
  * than min(k, window) candidates); its result is the exhaustive window
  * search. d_out_shortlist (optional, [nq][k] int64) receives each query's
  * shortlist by descending score, -1 past the window's size and for fallback
- * queries. Same query arguments as homs_search_window. Asynchronous; grows
+ * queries. Same query arguments as homs_search_window. The model's embed size
+ * must be 64, 128 or 256 (HOMS_E_UNSUPPORTED otherwise). Asynchronous; grows
  * the context's workspace on first use of a larger nq.
  */
 homs_status homs_search_learned(homs_ctx *ctx, homs_model *model, int64_t nq,
