@@ -244,24 +244,32 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
 // cores and appends every in-window pair at or above the query's threshold.
-// The tile's query embeddings are the B operands of every step, so each wave
-// keeps its two 32-query columns in registers for the whole chunk (E / 16
-// operand registers of 16 bytes per column); library rows go through one LDS
-// buffer (rows padded by 16 bytes, so the 32 lanes of a column read distinct
-// banks), and the next block's rows are loaded into registers while the
-// current block is multiplied, a whole block of matrix work ahead of use.
-// The epilogue tests each of the lane's 64 pairs with one compare when the
-// wave's 64 rows lie inside the lane's windows. Hits are rare; a position is
-// skipped unless some lane of the wave hits (a scalar branch on the ballot),
-// and hits are appended to the wave's own LDS list at positions counted from
-// the ballot (no atomics), which the wave flushes to the per-query global
-// buffers when it is nearly full and at the end: the global atomics of a
-// flush are independent, so their latency overlaps instead of stalling every
-// hit.
-constexpr int kWaveList = 2048;  // LDS entries per wave
+//
+// Eight waves, two per SIMD, so that one wave's epilogue runs while the other
+// wave's matrix instructions do: wave (wr, wn) owns rows 64 wr .. + 63 (two
+// 32-row tiles) of each block and the 32 queries of column wn, whose
+// embeddings are its B operands for the whole chunk (E / 16 registers of 16
+// bytes). Library rows stream through two LDS buffers filled by direct
+// global-to-LDS loads (global_load_lds_dwordx4, no staging registers) two
+// blocks ahead of their use, one padded row per half-wave load so that every
+// A read is a base plus an immediate and the 16 rows read together by a
+// quarter-wave hit distinct banks. The loads are issued from inline asm with
+// explicit vmcnt waits: the compiler would otherwise drain every outstanding
+// LDS load before any LDS read and cap the prefetch at one block.
+//
+// Epilogue: one compare per pair when the lane's 60 rows of the block lie
+// inside its window (the usual case); a position is skipped unless some lane
+// of the wave hits (a scalar branch on the ballot); hits go to the wave's own
+// LDS list at positions counted from the ballot (no atomics, no global
+// loads), which is flushed to the per-query global buffers when half full
+// and at the end.
+constexpr int kWaveList = 256;  // LDS entries per wave
+
+// s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
 
 template <int E>
-__global__ __launch_bounds__(256, 1) void collect_kernel(
+__global__ __launch_bounds__(512, 1) void collect_kernel(
     int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
@@ -270,17 +278,18 @@ __global__ __launch_bounds__(256, 1) void collect_kernel(
     uint32_t* __restrict__ count, uint64_t* __restrict__ buf)
 {
     using namespace gemm;
-    constexpr int KS = E / 16;              // 32 x 32 x 16 steps
-    constexpr int RB = E * 2 + 16;          // LDS bytes per library row
-    constexpr int PIECES = E / 8;           // 16-byte pieces per row
-    constexpr int PPT = 128 * PIECES / 256; // pieces per thread per block
-    __shared__ __attribute__((aligned(16))) uint8_t sA[128 * RB];
-    __shared__ uint64_t s_key[4][kWaveList];
-    __shared__ uint8_t s_col[4][kWaveList];  // query of the entry within the tile
+    constexpr int KS = E / 16;                    // 32 x 32 x 16 steps
+    constexpr int RB = E * 2 + 16;                // LDS bytes per library row (padded)
+    constexpr int PIECES = E / 8;                 // 16-byte pieces per row
+    constexpr int NW = 8;                         // waves
+    constexpr int NI = 128 / NW;                  // rows (direct loads) per wave per block
+    static_assert(PIECES <= 64 && NI < 64, "one row per load, vmcnt range");
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * RB];
+    __shared__ uint64_t s_key[NW][kWaveList];
+    __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
     // Chunks are fixed row ranges of the sorted library (blockIdx.y), clipped
     // to the tile's candidate range: the workgroups of all tiles that cover a
-    // chunk run together (x varies fastest) and read the same rows, which
-    // then come from L2 instead of HBM.
+    // chunk run together (x varies fastest) and read the same rows.
     const int64_t tile = blockIdx.x;
     const int64_t r0 = (int64_t)blockIdx.y * kCollectChunk;
     const int64_t c0 = max(r0, tile_lo[tile]);
@@ -288,113 +297,151 @@ __global__ __launch_bounds__(256, 1) void collect_kernel(
     if (c0 >= c1) return;
     const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
-    const int64_t qlast = q_end - 1;
+    const int nblk = (int)((c1 - c0 + 127) / 128);
 
-    // the two query columns of this lane: epilogue state and B operands
-    int64_t qlo[2], qhi[2], qslot[2];
-    float qthr[2];
-    bf16x8 bq[2][KS];
+    // rows [c0 + 128 b, + 128) into sA[b & 1]: load x of wave w moves row
+    // NI w + x, lane l < PIECES its piece l, to consecutive LDS bytes (the
+    // destination of a direct load is M0 + 16 x lane)
+    auto issue = [&](int b) {
+        const int64_t mb = c0 + (int64_t)b * 128;
+        const uint32_t base = (uint32_t)(uintptr_t)&sA[b & 1][0];
+        const uint16_t* gbase = lib_emb + (size_t)mb * E;  // wave-uniform
+        const int last = (int)min((int64_t)127, c1 - 1 - mb);  // rows past c1 repeat the last
+        if (l < PIECES) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int64_t p = p0 + wn * 64 + j * 32 + (l & 31);
-        qslot[j] = p < q_end ? p - q_begin : -1;
-        qlo[j] = qhi[j] = 0;
-        qthr[j] = INFINITY;
-        if (p < q_end) {
-            const uint32_t qi = qperm[p];
-            qlo[j] = lo[qi];
-            qhi[j] = hi[qi];
-            qthr[j] = thr[p];
+            for (int x = 0; x < NI; ++x) {
+                const int row = w * NI + x;
+                const uint32_t voff = (uint32_t)(min(row, last) * (E * 2) + l * 16);
+                const uint32_t lds = __builtin_amdgcn_readfirstlane(base + (uint32_t)(row * RB));
+                asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                             :
+                             : "v"(voff), "s"(gbase), "s"(lds)
+                             : "memory", "m0");
+            }
         }
-        const uint16_t* qrow = q_sorted + (size_t)min(p, qlast) * E + 8 * (l >> 5);
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) bq[j][kk] = *(const bf16x8*)(qrow + kk * 16);
+    };
+
+    // this lane's query column: epilogue state (32-bit rows: the library has
+    // fewer than 2^31 rows) and B operands
+    const int col = wn * 32 + (l & 31);
+    const int64_t p = p0 + col;
+    const bool qok = p < q_end;
+    uint32_t qlo = 0, qhi = 0;
+    float qthr = INFINITY;
+    if (qok) {
+        const uint32_t qi = qperm[p];
+        qlo = (uint32_t)lo[qi];
+        qhi = (uint32_t)hi[qi];
+        qthr = thr[p];
     }
+    bf16x8 bq[KS];
+    {
+        const uint16_t* qrow = q_sorted + (size_t)min(p, q_end - 1) * E + 8 * (l >> 5);
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) bq[kk] = *(const bf16x8*)(qrow + kk * 16);
+    }
+    const uint32_t e1 = (uint32_t)c1;
+    // The B operands are in registers before the pipeline starts, so that no
+    // wait for them is left inside the loop, where it would also wait for the
+    // prefetched blocks (vmcnt counts in issue order).
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    issue(0);
+    if (nblk > 1) issue(1);
 
     // the wave's LDS hit list and its flush to the per-query global buffers
     uint32_t wcount = 0;  // wave-uniform
     const int64_t qbase = tile * kTileQ;  // pass slot of the tile's first query
+    // one hit straight to the global buffer (score key << 32 | sorted row v)
+    auto put = [&](int64_t qs, uint64_t v) {
+        const uint32_t slot = atomicAdd(count + qs, 1u);
+        if (slot < (uint32_t)kCapacity)
+            buf[(size_t)qs * kCapacity + slot] =
+                (v & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
+    };
+    // the wave's list to the global buffers, four entries per lane at a time
+    // so that their atomics and lookups are in flight together
     auto flush = [&]() {
-        for (uint32_t e = (uint32_t)l; e < wcount; e += 64) {
-            const int64_t qs = qbase + s_col[w][e];
-            const uint32_t slot = atomicAdd(count + qs, 1u);
-            if (slot < (uint32_t)kCapacity) buf[(size_t)qs * kCapacity + slot] = s_key[w][e];
+        for (uint32_t e0 = 0; e0 < wcount; e0 += 256) {
+            uint32_t slot[4], orig[4];
+            int64_t qs[4];
+            uint64_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t e = e0 + 64 * u + l;
+                qs[u] = e < wcount ? qbase + s_col[w][e] : -1;
+                v[u] = e < wcount ? s_key[w][e] : 0;
+                slot[u] = qs[u] >= 0 ? atomicAdd(count + qs[u], 1u) : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                orig[u] = slot[u] < (uint32_t)kCapacity ? lib_orig[(uint32_t)v[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (slot[u] < (uint32_t)kCapacity)
+                    buf[(size_t)qs[u] * kCapacity + slot[u]] =
+                        (v[u] & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - orig[u]);
         }
         wcount = 0;
     };
 
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    u32x4 stg[PPT];
-#pragma unroll
-    for (int x = 0; x < PPT; ++x) {
-        const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
-        stg[x] = *(const u32x4*)(lib_emb + (size_t)min(c0 + row, c1 - 1) * E + part * 8);
-    }
-    for (int64_t m0 = c0; m0 < c1; m0 += 128) {
-        __syncthreads();  // the previous block's readers are done with sA
-#pragma unroll
-        for (int x = 0; x < PPT; ++x) {
-            const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
-            *(u32x4*)(sA + row * RB + part * 16) = stg[x];
-        }
+    for (int b = 0; b < nblk; ++b) {
+        // block b has landed: the loads of block b + 1 (if any) may stay in flight
+        if (b + 1 < nblk)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(NI));
+        else
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
         __syncthreads();
-        const int64_t mn = m0 + 128 < c1 ? m0 + 128 : m0;  // the last block reloads itself
+        const uint8_t* Ar = sA[b & 1] + (wr * 64 + (l & 31)) * RB + 16 * (l >> 5);
+        f32x16 acc[2];
+        acc[0] = acc[1] = f32x16{0};
 #pragma unroll
-        for (int x = 0; x < PPT; ++x) {
-            const int c = t + 256 * x, row = c / PIECES, part = c % PIECES;
-            stg[x] = *(const u32x4*)(lib_emb + (size_t)min(mn + row, c1 - 1) * E + part * 8);
+        for (int kk = 0; kk < KS; ++kk) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 av = *(const bf16x8*)(Ar + i * 32 * RB + kk * 32);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[kk], acc[i], 0, 0, 0);
+            }
         }
-        __builtin_amdgcn_sched_barrier(0);  // the next block's loads go out first
-        f32x16 acc[2][2];
+        __syncthreads();  // every wave is done reading sA[b & 1]
+        if (b + 2 < nblk) issue(b + 2);
+
+        // the lane's rows are gl + off, off in [0, 59]; all inside when the
+        // window and the chunk cover [gl, gl + 60]
+        const uint32_t gl = (uint32_t)(c0 + (int64_t)b * 128) + wr * 64 + 4 * (l >> 5);
+        const bool inside = gl >= qlo && gl + 61 <= qhi && gl + 61 <= e1;
+        const float tj = inside ? qthr : INFINITY;  // fast path threshold
+        const bool edge = __ballot(!inside && qok) != 0;  // wave-uniform
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-            bf16x8 av[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                av[i] = *(const bf16x8*)(sA + (wr * 64 + i * 32 + (l & 31)) * RB + kk * 32 +
-                                         16 * (l >> 5));
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bq[j][kk],
-                                                                       acc[i][j], 0, 0, 0);
-        }
-        const int64_t w0 = m0 + wr * 64;  // first row of this wave's 64
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const bool inside = w0 >= qlo[j] && w0 + 64 <= qhi[j] && w0 + 64 <= c1;
-            const uint8_t col = (uint8_t)(wn * 64 + j * 32 + (l & 31));
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t g = w0 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-                    const float sc = acc[i][j][r];
-                    const bool ok = sc >= qthr[j] &&
-                                    (inside || (g < c1 && g >= qlo[j] && g < qhi[j]));
-                    const uint64_t m = __ballot(ok);
-                    if (m != 0) {  // wave-uniform
-                        if (wcount + 64 > kWaveList) {
-                            flush();
-                        }
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t g = gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3));
+                const float sc = acc[i][r];
+                bool ok = sc >= tj;
+                if (edge)  // some lane's window or the chunk ends inside this block
+                    ok = ok || (!inside && sc >= qthr && g < e1 && g >= qlo && g < qhi);
+                const uint64_t m = __ballot(ok);
+                if (m != 0) {  // wave-uniform
+                    const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
+                    if (wcount + 64 <= kWaveList) {
+                        // the sorted row for now: its library index is looked up at
+                        // the flush, so no global load (and no vmcnt wait, which
+                        // would also drain the prefetch) happens here
                         if (ok) {
                             const uint32_t pos =
                                 wcount + __builtin_amdgcn_mbcnt_hi(
                                              (uint32_t)(m >> 32),
                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            s_key[w][pos] = ((uint64_t)fkey(sc) << 32) |
-                                            (uint64_t)(0xFFFFFFFFu - lib_orig[g]);
-                            s_col[w][pos] = col;
+                            s_key[w][pos] = v;
+                            s_col[w][pos] = (uint8_t)col;
                         }
                         wcount += (uint32_t)__popcll(m);
+                    } else if (ok) {  // list full inside a dense block: direct
+                        put(qbase + col, v);
                     }
                 }
-        }
+            }
+        if (wcount > kWaveList / 2) flush();  // wave-uniform, at most once per block
     }
     flush();
 }
@@ -572,13 +619,13 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
         const dim3 cgrid((uint32_t)tiles, (uint32_t)max_chunks);
         if (E == 256)
-            collect_kernel<256><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+            collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
                                                       thi, m->lib_emb, c->lib.orig, count, buf);
         else if (E == 128)
-            collect_kernel<128><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+            collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
                                                       thi, m->lib_emb, c->lib.orig, count, buf);
         else
-            collect_kernel<64><<<cgrid, 256, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
+            collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
                                                      thi, m->lib_emb, c->lib.orig, count, buf);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
