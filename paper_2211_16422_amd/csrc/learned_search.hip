@@ -409,38 +409,51 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         // window and the chunk cover [gl, gl + 60]
         const uint32_t gl = (uint32_t)(c0 + (int64_t)b * 128) + wr * 64 + 4 * (l >> 5);
         const bool inside = gl >= qlo && gl + 61 <= qhi && gl + 61 <= e1;
-        const float tj = inside ? qthr : INFINITY;  // fast path threshold
-        const bool edge = __ballot(!inside && qok) != 0;  // wave-uniform
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t g = gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3));
-                const float sc = acc[i][r];
-                bool ok = sc >= tj;
-                if (edge)  // some lane's window or the chunk ends inside this block
-                    ok = ok || (!inside && sc >= qthr && g < e1 && g >= qlo && g < qhi);
-                const uint64_t m = __ballot(ok);
-                if (m != 0) {  // wave-uniform
-                    const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
-                    if (wcount + 64 <= kWaveList) {
-                        // the sorted row for now: its library index is looked up at
-                        // the flush, so no global load (and no vmcnt wait, which
-                        // would also drain the prefetch) happens here
-                        if (ok) {
-                            const uint32_t pos =
-                                wcount + __builtin_amdgcn_mbcnt_hi(
-                                             (uint32_t)(m >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            s_key[w][pos] = v;
-                            s_col[w][pos] = (uint8_t)col;
-                        }
-                        wcount += (uint32_t)__popcll(m);
-                    } else if (ok) {  // list full inside a dense block: direct
-                        put(qbase + col, v);
-                    }
+        // append the hits of one position (m: the wave's hit mask, uniform)
+        auto append = [&](uint64_t m, bool ok, float sc, uint32_t g) {
+            const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
+            if (wcount + 64 <= kWaveList) {
+                // the sorted row for now: its library index is looked up at the
+                // flush, so no global load (and no vmcnt wait, which would also
+                // drain the prefetch) happens here
+                if (ok) {
+                    const uint32_t pos =
+                        wcount + __builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    s_key[w][pos] = v;
+                    s_col[w][pos] = (uint8_t)col;
                 }
+                wcount += (uint32_t)__popcll(m);
+            } else if (ok) {  // list full inside a dense block: direct
+                put(qbase + col, v);
             }
+        };
+        if (__ballot(!inside && qok) == 0) {
+            // every lane's 60 rows lie inside its window: one compare per pair
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float sc = acc[i][r];
+                    const uint64_t m = __ballot(sc >= qthr);
+                    if (m != 0)
+                        append(m, sc >= qthr, sc,
+                               gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3)));
+                }
+        } else {
+            // some lane's window or the chunk ends inside this block
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t g = gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3));
+                    const float sc = acc[i][r];
+                    const bool ok = sc >= qthr && g < e1 && g >= qlo && g < qhi;
+                    const uint64_t m = __ballot(ok);
+                    if (m != 0) append(m, ok, sc, g);
+                }
+        }
         if (wcount > kWaveList / 2) flush();  // wave-uniform, at most once per block
     }
     flush();
