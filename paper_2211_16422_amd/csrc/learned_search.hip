@@ -459,14 +459,24 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     flush();
 }
 
-// one workgroup per query of the pass: the k largest keys of its buffer
+// One workgroup per query of the pass: the k largest keys of its buffer, in
+// descending order. When more than k candidates were kept, the k-th largest
+// key is found by a radix select (8 bits per round, high 32 bits from LDS, low
+// 32 bits, which only separate equal scores, from the buffer), the keys at or
+// above it (exactly k: keys are unique) are gathered and only those are
+// sorted (bitonic, in LDS).
+constexpr int kMaxK = kCapacity / 8;  // largest k the search takes
+
 __global__ __launch_bounds__(kThreads) void select_kernel(
     int64_t q_begin, int k, const uint32_t* __restrict__ count, const uint64_t* __restrict__ buf,
     const float* __restrict__ thr, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t* __restrict__ shortlist,
     uint8_t* __restrict__ fallback)
 {
-    extern __shared__ uint64_t sk[];
+    extern __shared__ uint32_t s_hi[];  // [kCapacity] high halves of the keys
+    __shared__ uint64_t s_sel[kMaxK];
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_digit, s_above, s_nsel;
     const int64_t p = q_begin + blockIdx.x;
     const uint32_t qi = qperm[p];
     const int64_t w = hi[qi] - lo[qi];
@@ -475,17 +485,69 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
     const bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
-    int np = 1;
-    while (np < n) np <<= 1;
-    if (!bad) {
-        for (int i = threadIdx.x; i < np; i += blockDim.x)
-            sk[i] = i < n ? buf[(size_t)blockIdx.x * kCapacity + i] : 0ull;
+    const uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
+    const int kk = min(k, n);  // keys kept
+    if (!bad && kk > 0) {      // uniform
+        if (n <= kMaxK) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) s_sel[i] = keys[i];
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) s_hi[i] = (uint32_t)(keys[i] >> 32);
+            __syncthreads();
+            // radix select of the kk-th largest 64-bit key
+            uint64_t prefix = 0, mask = 0;
+            uint32_t r = (uint32_t)kk;
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+                __syncthreads();
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    // high rounds from LDS; low rounds only for keys whose high half matches
+                    const uint64_t hk = (uint64_t)s_hi[i] << 32;
+                    if (shift >= 32) {
+                        if ((hk & mask) == prefix) atomicAdd(&hist[(hk >> shift) & 255u], 1u);
+                    } else if ((hk & 0xFFFFFFFF00000000ull) == (prefix & 0xFFFFFFFF00000000ull)) {
+                        const uint64_t key = keys[i];
+                        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t above = 0;
+                    int d = 255;
+                    for (; d > 0; --d) {
+                        if (above + hist[d] >= r) break;
+                        above += hist[d];
+                    }
+                    s_digit = (uint32_t)d;
+                    s_above = above;
+                }
+                __syncthreads();
+                prefix |= (uint64_t)s_digit << shift;
+                mask |= (uint64_t)255 << shift;
+                r -= s_above;
+                __syncthreads();
+            }
+            // prefix is now the kk-th largest key: gather the kk keys at or above it
+            if (threadIdx.x == 0) s_nsel = 0;
+            __syncthreads();
+            const uint32_t thi = (uint32_t)(prefix >> 32);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const uint32_t h = s_hi[i];
+                if (h < thi) continue;
+                const uint64_t key = keys[i];
+                if (h > thi || key >= prefix) s_sel[atomicAdd(&s_nsel, 1u)] = key;
+            }
+        }
         __syncthreads();
-        if (n > 1) bitonic_desc(sk, np);
+        const int m = n <= kMaxK ? n : kk;  // keys now in s_sel
+        int np = 1;
+        while (np < m) np <<= 1;
+        for (int i = m + threadIdx.x; i < np; i += blockDim.x) s_sel[i] = 0ull;
+        __syncthreads();
+        if (np > 1) bitonic_desc(s_sel, np);
     }
     int64_t* out = shortlist + (size_t)qi * k;
     for (int i = threadIdx.x; i < k; i += blockDim.x)
-        out[i] = (!bad && i < n) ? (int64_t)(0xFFFFFFFFu - (uint32_t)sk[i]) : -1;
+        out[i] = (!bad && i < kk) ? (int64_t)(0xFFFFFFFFu - (uint32_t)s_sel[i]) : -1;
     if (threadIdx.x == 0) fallback[qi] = bad ? 1 : 0;
 }
 
@@ -568,7 +630,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int learned_max_k() { return kCapacity / 8; }
+int learned_max_k() { return kMaxK; }
 
 bool learned_search_supports(int E) { return E == 64 || E == 128 || E == 256; }
 
@@ -619,7 +681,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     if (e != hipSuccess) return e;
     const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
     if (max_chunks > 65535) return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)kCapacity * 8;
+    const size_t lds = (size_t)kCapacity * 4;
     for (int64_t b0 = 0; b0 < nq; b0 += plan.batch) {
         const int64_t b1 = std::min(nq, b0 + plan.batch), nb = b1 - b0;
         const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
