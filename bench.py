@@ -39,6 +39,7 @@ METRIC = "query-ref Hamming comparisons/s and queries/s at ±500 Da, D=8192"
 # (homs_measure_xor_popcount_rate) and reports the model beside it.
 VALU_MODEL_TOPS = 256 * 64 * 2.4e9 / 1e12
 MFMA_PEAK_TOPS = 5000.0  # dense fp8 / int8 matrix peak of MI355X, TFLOP/s (TOP/s)
+MFMA_F4_PEAK_TOPS = 10100.0  # dense fp4 (and fp6) matrix peak of MI355X, TFLOP/s
 
 # HBM bytes per launch of each search kernel on the default large workload,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
@@ -49,7 +50,16 @@ MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
+                  "mfma_fp4": ("search_mfma.hip", "mfma_direct.h"),
                   "mfma_int8": ("search_mfma.hip",)}
+
+# per engine: element format, dense matrix peak (TFLOP/s or TOP/s), kernel name, JSON dtype
+MFMA_ENGINES = {"mfma_fp8": ("fp8 e4m3", MFMA_PEAK_TOPS, "mfma_direct_kernel<0> (fp8 e4m3)",
+                             "fp8e4m3(+-1)->f32"),
+                "mfma_fp4": ("fp4 e2m1", MFMA_F4_PEAK_TOPS, "mfma_direct_kernel<4> (fp4 e2m1)",
+                             "fp4e2m1(+-1)->f32"),
+                "mfma_int8": ("int8", MFMA_PEAK_TOPS, "mfma_search_kernel (int8)",
+                              "i8(+-1)->i32")}
 
 
 VALU_PEAK_TOPS = VALU_MODEL_TOPS  # replaced by the live measurement in main()
@@ -82,7 +92,7 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baseline (for profiler runs)")
     ap.add_argument("--engine", default="mfma_fp8", choices=list(ENGINE_SOURCES),
-                    help="search engine of the timed step (all three are bit-exact)")
+                    help="search engine of the timed step (all are bit-exact)")
     ap.add_argument("--skip-mfma", action="store_true",
                     help="time only the step's engine (no side-by-side engine timings)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -153,7 +163,7 @@ def main():
     out_dist = torch.empty(q.n, dtype=torch.int32, device=dev)
 
     engines = {"popcount": h.ENGINE_POPCOUNT, "mfma_fp8": h.ENGINE_MFMA_F8,
-               "mfma_int8": h.ENGINE_MFMA_I8}
+               "mfma_fp4": h.ENGINE_MFMA_F4, "mfma_int8": h.ENGINE_MFMA_I8}
     engine = engines[args.engine]
 
     def step():
@@ -209,13 +219,12 @@ def main():
                     "ops_per_pair": 2 * words}
         ops = 2.0 * w.dim * pairs  # one multiply-add per component per pair
         ach = ops / (kernel_ms * 1e-3) / 1e12
-        fmt = "fp8 e4m3" if name == "mfma_fp8" else "int8"
-        return {"bound": "mfma", "achieved": round(ach, 1), "peak": MFMA_PEAK_TOPS,
-                "unit": "TFLOP/s" if name == "mfma_fp8" else "TOP/s",
-                "frac": round(ach / MFMA_PEAK_TOPS, 4), "traffic": traffic,
+        fmt, peak, kernel, _ = MFMA_ENGINES[name]
+        return {"bound": "mfma", "achieved": round(ach, 1), "peak": peak,
+                "unit": "TOP/s" if name == "mfma_int8" else "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic,
                 "peak_kind": f"dense {fmt} matrix peak of MI355X",
-                "kernel": ("mfma_direct_kernel (fp8 e4m3)" if name == "mfma_fp8" else
-                           "mfma_search_kernel (int8)"), "kernel_ms": round(kernel_ms, 3),
+                "kernel": kernel, "kernel_ms": round(kernel_ms, 3),
                 "ops_per_pair": 2 * w.dim}
 
     search_ms = prof["search_ms"] / max(prof["search_launches"], 1)
@@ -259,8 +268,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "comparisons/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"popcount": "u32", "mfma_fp8": "fp8e4m3(+-1)->f32",
-                  "mfma_int8": "i8(+-1)->i32"}[args.engine],
+        "dtype": "u32" if args.engine == "popcount" else MFMA_ENGINES[args.engine][3],
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {g.meta['n_ref']} references + {g.meta['n_decoy']} "
                                f"decoys, {q.n} queries, D={w.dim}, Q={w.n_levels}, "
@@ -356,13 +364,15 @@ def bench_batched(args, w, dev):
     same = bool(torch.equal(out_idx, ref_idx) and torch.equal(out_dist, ref_dist))
     words = w.dim // 32
     ms = prof["search_ms"] / max(prof["search_launches"], 1)
-    if best["engine"] == h.ENGINE_MFMA_F8:
+    if best["engine"] in (h.ENGINE_MFMA_F8, h.ENGINE_MFMA_F4):
+        name = "mfma_fp8" if best["engine"] == h.ENGINE_MFMA_F8 else "mfma_fp4"
+        fmt, peak, _, dtype = MFMA_ENGINES[name]
         tops = 2.0 * w.dim * pairs / (ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(tops, 1), "peak": MFMA_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": round(tops / MFMA_PEAK_TOPS, 4), "traffic": None,
-                "peak_kind": "dense fp8 e4m3 matrix peak of MI355X (wide tiles; narrow "
+        roof = {"bound": "mfma", "achieved": round(tops, 1), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(tops / peak, 4), "traffic": None,
+                "peak_kind": f"dense {fmt} matrix peak of MI355X (wide tiles; narrow "
                              "windows are scored by popcount in the same launch)",
-                "kernel": "batched graph (persistent_search_kernel<fp8> + planning)",
+                "kernel": f"batched graph (persistent_search_kernel<{fmt}> + planning)",
                 "kernel_ms": round(ms, 3)}
     else:
         tops = 2.0 * words * pairs / (ms * 1e-3) / 1e12
@@ -377,7 +387,7 @@ def bench_batched(args, w, dev):
         "value": pairs * args.steps / el, "unit": "comparisons/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8e4m3(+-1)->f32" if best["engine"] == h.ENGINE_MFMA_F8 else "u32",
+        "dtype": dtype if best["engine"] != h.ENGINE_POPCOUNT else "u32",
         "data": "synthetic",
         "config": {"workload": f"batched: {g.meta['n_ref']} references + {g.meta['n_decoy']} "
                                f"decoys, {q.n} queries (70% 20 ppm, 30% 500 Da), charges 2-4, "

@@ -90,14 +90,16 @@ typedef struct homs_window {
 
 /* Search engines for homs_search_window. POPCOUNT: XOR + population count
  * on packed words (Section 3.4 with the bit packing of Section 4.1).
- * MFMA_I8 / MFMA_F8: the same distances as H = (D - <x, y>) / 2 of the
- * bipolar vectors (Section 3.3), contracted on matrix cores with int8 +-1
- * (int32 accumulate) or fp8 e4m3 +-1.0 (fp32 accumulate) operands expanded
- * from the packed bits on the fly. Every partial sum is an integer of
- * magnitude <= D <= 32768, so all engines return identical results. */
+ * MFMA_I8 / MFMA_F8 / MFMA_F4: the same distances as H = (D - <x, y>) / 2
+ * of the bipolar vectors (Section 3.3), contracted on matrix cores with int8
+ * +-1 (int32 accumulate), fp8 e4m3 +-1.0 or fp4 e2m1 +-1.0 (fp32 accumulate)
+ * operands expanded from the packed bits on the fly. Every partial sum is an
+ * integer of magnitude <= D <= 32768, so all engines return identical
+ * results. */
 #define HOMS_ENGINE_POPCOUNT 0
 #define HOMS_ENGINE_MFMA_I8 1
 #define HOMS_ENGINE_MFMA_F8 2
+#define HOMS_ENGINE_MFMA_F4 3
 
 /* Fills *p with Table 1 / Section 4.2 defaults (D = 8192, Q = 16, top 50,
  * [101, 1500) m/z, 0.05 Da bins, 1% noise floor, alpha = D/2, charge match,
@@ -228,9 +230,9 @@ homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv
  *  narrow_group  narrow queries per work item, a multiple of 4 (>= 4).
  *  grid          workgroups of the persistent kernel (1..65535).
  *  bucket_da     precursor bucket width (Da) used to order queries into tiles.
- *  engine        how wide tiles are scored: HOMS_ENGINE_POPCOUNT or
- *                HOMS_ENGINE_MFMA_F8 (the default; both exact, see
- *                homs_search_window).
+ *  engine        how wide tiles are scored: HOMS_ENGINE_POPCOUNT,
+ *                HOMS_ENGINE_MFMA_F8 (the default) or HOMS_ENGINE_MFMA_F4
+ *                (all exact, see homs_search_window).
  */
 typedef struct homs_batched_config {
     uint32_t narrow_max;

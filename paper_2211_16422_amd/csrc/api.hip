@@ -535,7 +535,7 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     std::string why;
     if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
     if (engine != HOMS_ENGINE_POPCOUNT && engine != HOMS_ENGINE_MFMA_I8 &&
-        engine != HOMS_ENGINE_MFMA_F8)
+        engine != HOMS_ENGINE_MFMA_F8 && engine != HOMS_ENGINE_MFMA_F4)
         return fail(c, HOMS_E_INVALID, "unknown engine");
     if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
     if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
@@ -568,7 +568,10 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
                                                 w.tile_hi, plan, w.keys, s),
                 "search kernel");
     else
-        HIP_TRY(c, homs::launch_search_mfma(c, engine == HOMS_ENGINE_MFMA_I8 ? 0 : 1, nq, d_q_hv,
+        HIP_TRY(c, homs::launch_search_mfma(c, engine == HOMS_ENGINE_MFMA_I8   ? 0
+                                               : engine == HOMS_ENGINE_MFMA_F8 ? 1
+                                                                               : 2,
+                                            nq, d_q_hv,
                                             qperm, w.lo, w.hi, w.tile_lo, w.tile_hi, w.keys, s),
                 "MFMA search kernel");
     hipEvent_t e2 = prof_mark(c, s);
@@ -606,8 +609,9 @@ bool batched_config_valid(const homs_batched_config* b, std::string* why)
         *why = "bucket_da must be finite and > 0";
         return false;
     }
-    if (b->engine != HOMS_ENGINE_POPCOUNT && b->engine != HOMS_ENGINE_MFMA_F8) {
-        *why = "engine must be HOMS_ENGINE_POPCOUNT or HOMS_ENGINE_MFMA_F8";
+    if (b->engine != HOMS_ENGINE_POPCOUNT && b->engine != HOMS_ENGINE_MFMA_F8 &&
+        b->engine != HOMS_ENGINE_MFMA_F4) {
+        *why = "engine must be HOMS_ENGINE_POPCOUNT, HOMS_ENGINE_MFMA_F8 or HOMS_ENGINE_MFMA_F4";
         return false;
     }
     return true;
@@ -790,7 +794,7 @@ homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_h
     const uint32_t grids[] = {512, 1024, 2048, 4096};
     const uint32_t narrows[] = {256, 1024, 4096};
     const uint32_t groups[] = {16, 32, 64};
-    const uint32_t engines[] = {HOMS_ENGINE_POPCOUNT, HOMS_ENGINE_MFMA_F8};
+    const uint32_t engines[] = {HOMS_ENGINE_POPCOUNT, HOMS_ENGINE_MFMA_F8, HOMS_ENGINE_MFMA_F4};
     auto sweep = [&](auto set, const uint32_t* vals, int n) {
         for (int i = 0; i < n && st == HOMS_OK; ++i) {
             homs::BatchedConfig cand = cur;

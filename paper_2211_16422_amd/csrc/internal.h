@@ -36,7 +36,7 @@ struct BatchedConfig {
     uint32_t narrow_group = 32;   // narrow queries per work item (multiple of 4)
     uint32_t grid = 1024;         // persistent workgroups
     double bucket_da = 0.5;       // precursor bucket width for query ordering
-    int32_t engine = HOMS_ENGINE_MFMA_F8;  // wide tiles: popcount or fp8 matrix cores
+    int32_t engine = HOMS_ENGINE_MFMA_F8;  // wide tiles: popcount, fp8 or fp4 matrix cores
 };
 
 // A captured batched search, replayed while its arguments stay the same.
@@ -139,7 +139,7 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
                                  const double* values, int64_t* out_idx, int32_t* out_dist,
                                  hipStream_t s);
 
-// search_mfma.hip (fmt 0: int8, 1: fp8 e4m3)
+// search_mfma.hip (fmt 0: int8, 1: fp8 e4m3, 2: fp4 e2m1)
 int search_mfma_tile();
 int64_t search_mfma_row_pad();  // rows of padding the library's orig array needs
 hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint32_t* q_hv,

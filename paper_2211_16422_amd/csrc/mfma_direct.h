@@ -1,17 +1,20 @@
-// Register-direct fp8 search tile: scores library rows [a, b) of the sorted
-// library against the 256 m/z-ordered queries of tile `tile` (positions
-// tile * 256 .. in qperm, of which the first nq exist) on matrix cores and
-// merges each query's best (distance, library index) into keys[] with one
-// 64-bit atomicMin. Used by the fp8 engine of the one-shot search and by the
-// batched persistent search. Needs a workgroup of 512 threads (8 waves in a
-// 2 x 4 grid, each owning 128 rows x 64 queries of a 256 x 256 block), D a
+// Register-direct matrix-core search tile: scores library rows [a, b) of the
+// sorted library against the 256 m/z-ordered queries of tile `tile`
+// (positions tile * 256 .. in qperm, of which the first nq exist) and merges
+// each query's best (distance, library index) into keys[] with one 64-bit
+// atomicMin. Used by the fp8 and fp4 engines of the one-shot search and by
+// the batched persistent search. Needs a workgroup of 512 threads (8 waves in
+// a 2 x 4 grid, each owning 128 rows x 64 queries of a 256 x 256 block), D a
 // multiple of 512, and an orig array padded by 256 entries past the library.
 //
 // With bit 0 = +1 and bit 1 = -1, H = (D - <x, y>) / 2 and <x, y> is exact in
 // fp32 (integers of magnitude <= D), so the distances equal the popcount
-// ones bit for bit. No LDS: every lane loads the packed bits of its own
-// operand rows from global memory one group (256 components) ahead and
-// expands them in registers right before the matrix instructions.
+// ones bit for bit. +-1 is exact in both element formats (fp8 e4m3 0x38 /
+// 0xB8, fp4 e2m1 0x2 / 0xA), and so is every product. No LDS: every lane
+// loads the packed bits of its own operand rows from global memory one group
+// (256 components) ahead and expands them in registers right before the
+// matrix instructions. fp4 operands take half the register bytes and half
+// the matrix cycles of fp8 ones for the same 64 components.
 #pragma once
 
 #include "internal.h"
@@ -46,6 +49,32 @@ __device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t
   return o;
 }
 
+// 32 packed bits -> 32 fp4 e2m1 nibbles of +-1.0 (0x2 / 0xA) in the low four
+// dwords of the operand (the fp4 form reads no others). Nibble j of dword m
+// carries bit m + 4 j in its sign position: one shift and one bit insert per
+// 8 components, the same order for both operands.
+__device__ __forceinline__ v8i expand_pm1_fp4(uint32_t w, uint32_t sel, uint32_t one) {
+  v8i o = v8i{0};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t x = w << (3 - m);
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(one));
+    o[m] = (int)r;
+  }
+  return o;
+}
+
+// element format code of the f8f6f4 matrix instruction: 0 = fp8 e4m3, 4 = fp4 e2m1
+template <int F>
+__device__ __forceinline__ v8i expand_pm1(uint32_t w, uint32_t sel, uint32_t one) {
+  static_assert(F == 0 || F == 4, "fp8 e4m3 or fp4 e2m1");
+  if constexpr (F == 0)
+    return expand_pm1_fp8(w, sel, one);
+  else
+    return expand_pm1_fp4(w, sel, one);
+}
+
 // Operand loads: within a group of 256 components (8 words per row), k half h
 // of every 32 x 32 x 64 step takes words 4h .. 4h + 3 of the group, stage s
 // word 4h + s, so each lane fetches 16 bytes per row per group; A (library
@@ -53,6 +82,7 @@ __device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t
 // while the current one is expanded and multiplied. The four waves of a row
 // half share library rows, and the two waves of a query quarter share query
 // rows, through L1.
+template <int F>
 __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
@@ -81,7 +111,7 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
   }
   const uint32_t G = words / 8;
   const uint32_t nblk = (b - a + MR - 1) / MR;
-  uint32_t sel = 0x80808080u, one = 0x38383838u;
+  uint32_t sel = F == 0 ? 0x80808080u : 0x88888888u, one = F == 0 ? 0x38383838u : 0x22222222u;
   asm volatile("" : "+v"(sel), "+v"(one));  // keep both in VGPRs
 
   for (uint32_t blk = 0; blk < nblk; ++blk) {
@@ -113,15 +143,15 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
 #pragma unroll
         for (int j = 0; j < TQ; ++j) {
           const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
-          bv[j] = expand_pm1_fp8(x, sel, one);
+          bv[j] = expand_pm1<F>(x, sel, one);
         }
 #pragma unroll
         for (int i = 0; i < TR; ++i) {
           const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
-          const v8i av = expand_pm1_fp8(x, sel, one);
+          const v8i av = expand_pm1<F>(x, sel, one);
 #pragma unroll
           for (int j = 0; j < TQ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], 0, 0,
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], F, F,
                                                                          0, 0, 0, 0);
         }
       }

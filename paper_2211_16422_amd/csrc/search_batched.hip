@@ -187,8 +187,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     }
 }
 
-// ENGINE 0: popcount tiles, 256 threads; ENGINE 2: fp8 matrix-core tiles
-// (mfd::tile_rows), 512 threads. Narrow queries are spread over the waves.
+// ENGINE 0: popcount tiles, 256 threads; ENGINE 2 / 3: fp8 / fp4 matrix-core
+// tiles (mfd::tile_rows), 512 threads. Narrow queries are spread over the waves.
 template <int ENGINE>
 __global__ __launch_bounds__(ENGINE == 0 ? popc::kTile : mfd::kThreads) void
 persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
@@ -200,7 +200,8 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                          const uint32_t* __restrict__ lib_hv,
                          const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
 {
-    static_assert(popc::kTile == mfd::kQueries, "both engines use 256-query tiles");
+    static_assert(popc::kTile == mfd::kQueries, "all engines use 256-query tiles");
+    constexpr int kFormat = ENGINE == HOMS_ENGINE_MFMA_F4 ? 4 : 0;  // f8f6f4 element format
     __shared__ uint32_t s_item;
     const uint32_t n_wide = plan->n_wide;
     const uint32_t wide_items = plan->wide_items;
@@ -230,8 +231,8 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                     popc::popcount_tile_rows(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
                                              (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
                 else
-                    mfd::tile_rows(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
-                                   (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
+                    mfd::tile_rows<kFormat>(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
+                                            (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
             }
         } else {
             const int64_t first = (int64_t)n_wide + (int64_t)(item - wide_items) * narrow_group;
@@ -306,6 +307,10 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
     fill_u64_kernel<<<blocks_for(nq), kThreads, 0, s>>>(keys, nq, ~0ull);
     if (cfg.engine == HOMS_ENGINE_MFMA_F8)
         persistent_search_kernel<HOMS_ENGINE_MFMA_F8><<<cfg.grid, mfd::kThreads, 0, s>>>(
+            c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
+    else if (cfg.engine == HOMS_ENGINE_MFMA_F4)
+        persistent_search_kernel<HOMS_ENGINE_MFMA_F4><<<cfg.grid, mfd::kThreads, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
             cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
     else

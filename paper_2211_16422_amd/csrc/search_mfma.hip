@@ -21,11 +21,11 @@
 // padded to 80 bytes so 16 lanes of a 16-byte LDS read touch 64 distinct
 // banks) is double-buffered in LDS while the other buffer feeds the MFMAs.
 //
-// fp8 engine (mfma_direct_kernel): no LDS. Every lane loads the packed bits
-// of its own operand rows and expands them in registers right before the
-// matrix instructions, with one shift and one bit insert per 4 bytes; the
-// LDS variant of this engine spent as many LDS cycles on operand traffic as
-// matrix cycles.
+// fp8 and fp4 engines (mfma_direct_kernel<F>): no LDS. Every lane loads the
+// packed bits of its own operand rows and expands them in registers right
+// before the matrix instructions, with one shift and one bit insert per 4
+// (fp8) or 8 (fp4) components; an LDS variant of the fp8 engine spent as
+// many LDS cycles on operand traffic as matrix cycles.
 //
 // Epilogue per block: distance = (D - dot) / 2, masked by each query's own
 // window and the chunk end, folded into a per-lane 64-bit running minimum of
@@ -212,19 +212,37 @@ __global__ __launch_bounds__(64 * WR * WQ, 1) void mfma_search_kernel(uint32_t w
   }
 }
 
+// XCD-aware work map of the register-direct kernels. Workgroups are handed
+// to the eight XCDs in turn (workgroup i to XCD i mod 8), and each XCD has its
+// own L2. Work items are (query tile, library chunk) pairs on absolute chunk
+// boundaries; they are grouped into patches of 4 adjacent tiles x 8 adjacent
+// chunks, and consecutive patches go to consecutive XCDs, so the 32
+// workgroups an XCD runs side by side share 8 chunks of library rows and 4
+// tiles of query rows (about 3 MB per 256-row step) in their L2.
+constexpr int kXcds = 8, kPatchTiles = 4, kPatchChunks = 8;
+constexpr int kPatch = kPatchTiles * kPatchChunks;
+
+template <int F>
 __global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
     const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig, uint64_t* __restrict__ keys,
-    int64_t chunk)
+    int64_t chunk, int64_t n_tiles, int64_t chunk_patches, int64_t patches)
 {
-  const int64_t tile = blockIdx.x;
-  const int64_t a64 = tlo[tile] + (int64_t)blockIdx.y * chunk;
-  const int64_t t_hi = thi[tile];
-  if (a64 >= t_hi) return;
-  mfd::tile_rows(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64,
-                 (uint32_t)min(a64 + chunk, t_hi), lib, orig, keys);
+  const int64_t wg = blockIdx.x;
+  const int64_t slot = wg / kXcds;  // position in this XCD's sequence
+  const int64_t patch = (slot / kPatch) * kXcds + wg % kXcds;
+  if (patch >= patches) return;
+  const int local = (int)(slot % kPatch);
+  const int64_t tile = (patch / chunk_patches) * kPatchTiles + local / kPatchChunks;
+  const int64_t cidx = (patch % chunk_patches) * kPatchChunks + local % kPatchChunks;
+  if (tile >= n_tiles) return;
+  const int64_t a64 = max(cidx * chunk, tlo[tile]);
+  const int64_t b64 = min(cidx * chunk + chunk, thi[tile]);
+  if (a64 >= b64) return;
+  mfd::tile_rows<F>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64, (uint32_t)b64, lib,
+                    orig, keys);
 }
 
 constexpr int kMfWR = 2, kMfWQ = 4, kMfTR = 4, kMfTQ = 2;
@@ -250,10 +268,22 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
         mfma_search_kernel<0, kMfWR, kMfWQ, kMfTR, kMfTQ><<<grid, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
             kMfChunk);
-    else
-        mfma_direct_kernel<<<grid, block, 0, s>>>(
-            c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
-            kMfChunk);
+    else {
+        const int64_t tile_groups = (n_tiles + kPatchTiles - 1) / kPatchTiles;
+        const int64_t chunk_patches = (max_chunks + kPatchChunks - 1) / kPatchChunks;
+        const int64_t patches = tile_groups * chunk_patches;
+        // whole rounds of kXcds patches, so every XCD's sequence is complete
+        const int64_t blocks = (patches + kXcds - 1) / kXcds * kXcds * kPatch;
+        if (blocks > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
+        if (fmt == 1)
+            mfma_direct_kernel<0><<<(uint32_t)blocks, block, 0, s>>>(
+                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
+                kMfChunk, n_tiles, chunk_patches, patches);
+        else
+            mfma_direct_kernel<4><<<(uint32_t)blocks, block, 0, s>>>(
+                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
+                kMfChunk, n_tiles, chunk_patches, patches);
+    }
     return hipGetLastError();
 }
 

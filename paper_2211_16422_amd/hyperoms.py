@@ -38,6 +38,7 @@ TOL_PPM = 1
 ENGINE_POPCOUNT = 0
 ENGINE_MFMA_I8 = 1
 ENGINE_MFMA_F8 = 2
+ENGINE_MFMA_F4 = 3
 
 
 class HomsError(RuntimeError):

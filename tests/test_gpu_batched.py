@@ -68,7 +68,7 @@ def test_mixed_windows_have_both_classes(mixed):
     assert narrow.max() < 64 and wide.min() > 64 and set(np.unique(g.queries.charge)) == {2, 3, 4}
 
 
-ENGINES = [0, 2]  # wide tiles by popcount, by fp8 matrix cores
+ENGINES = [0, 2, 3]  # wide tiles by popcount, by fp8 or fp4 matrix cores
 
 
 @pytest.mark.parametrize("engine", ENGINES)

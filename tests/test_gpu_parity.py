@@ -96,7 +96,7 @@ def test_every_distance(tiny):
         assert np.array_equal(dist[a:b][order], o_dist[a:b])
 
 
-ENGINES = [0, 1, 2]  # popcount, MFMA int8, MFMA fp8
+ENGINES = [0, 1, 2, 3]  # popcount, MFMA int8, MFMA fp8, MFMA fp4
 
 
 @pytest.mark.parametrize("engine", ENGINES)
