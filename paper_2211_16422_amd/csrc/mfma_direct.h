@@ -1,20 +1,27 @@
-// Register-direct matrix-core search tile: scores library rows [a, b) of the
-// sorted library against the 256 m/z-ordered queries of tile `tile`
-// (positions tile * 256 .. in qperm, of which the first nq exist) and merges
-// each query's best (distance, library index) into keys[] with one 64-bit
-// atomicMin. Used by the fp8 and fp4 engines of the one-shot search and by
-// the batched persistent search. Needs a workgroup of 512 threads (8 waves in
-// a 2 x 4 grid, each owning 128 rows x 64 queries of a 256 x 256 block), D a
-// multiple of 512, and an orig array padded by 256 entries past the library.
+// Matrix-core search tile (fp8 and fp4 engines of the one-shot search and the
+// batched persistent search): scores library rows [a, b) of the sorted
+// library against the 256 m/z-ordered queries of tile `tile` (positions
+// tile * 256 .. in qperm, of which the first nq exist) and merges each
+// query's best (distance, library index) into keys[] with one 64-bit
+// atomicMin. Needs a workgroup of 512 threads (8 waves in a 2 x 4 grid, each
+// owning 128 rows x 64 queries of a 256 x 256 block), D a multiple of 512,
+// and an orig array padded by 256 entries past the library.
 //
 // With bit 0 = +1 and bit 1 = -1, H = (D - <x, y>) / 2 and <x, y> is exact in
 // fp32 (integers of magnitude <= D), so the distances equal the popcount
 // ones bit for bit. +-1 is exact in both element formats (fp8 e4m3 0x38 /
-// 0xB8, fp4 e2m1 0x2 / 0xA), and so is every product. No LDS: every lane
-// loads the packed bits of its own operand rows from global memory one group
-// (256 components) ahead and expands them in registers right before the
-// matrix instructions. fp4 operands take half the register bytes and half
-// the matrix cycles of fp8 ones for the same 64 components.
+// 0xB8, fp4 e2m1 0x2 / 0xA), and so is every product. fp4 operands take half
+// the register bytes and half the matrix cycles of fp8 ones for the same 64
+// components.
+//
+// Data movement: the packed bits of the block's 256 library rows and 256
+// query rows move into LDS in stages of 4 groups (1,024 components, one
+// 128-byte line per row) by direct global-to-LDS loads, one stage ahead of
+// their use, with one barrier per stage; every wave reads its operands from
+// LDS (16 bytes per row and group) and expands them in registers right before
+// the matrix instructions. Staging loads every line once per workgroup
+// instead of once per wave, which was the bound of an earlier version whose
+// lanes loaded their own operand rows from global memory.
 #pragma once
 
 #include "internal.h"
@@ -29,6 +36,9 @@ constexpr int WR = 2, WQ = 4, TR = 4, TQ = 2;
 constexpr int kThreads = 64 * WR * WQ;   // 512
 constexpr int kRows = WR * TR * 32;      // library rows per block step (256)
 constexpr int kQueries = WQ * TQ * 32;   // queries per tile (256)
+
+// s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
 
 // 32 packed bits -> 32 fp8 e4m3 bytes of +-1.0 (0x38 / 0xB8). Byte j of dword
 // m carries bit m + 8 j in its sign position: one shift and one v_bfi_b32
@@ -75,30 +85,48 @@ __device__ __forceinline__ v8i expand_pm1(uint32_t w, uint32_t sel, uint32_t one
     return expand_pm1_fp4(w, sel, one);
 }
 
-// Operand loads: within a group of 256 components (8 words per row), k half h
-// of every 32 x 32 x 64 step takes words 4h .. 4h + 3 of the group, stage s
-// word 4h + s, so each lane fetches 16 bytes per row per group; A (library
-// rows) and B (queries) use the same assignment. The next group is in flight
-// while the current one is expanded and multiplied. The four waves of a row
-// half share library rows, and the two waves of a query quarter share query
-// rows, through L1.
-template <int F>
-__device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
+// Stage buffers: per stage, 256 library rows and 256 query rows of kSG * 32
+// bytes. The 16-byte piece p of row r is stored at position p ^ f(r) with
+// f(r) = (r / kRPB) mod kP, so that the 16 rows read together by a quarter
+// wave fall in 16 distinct bank groups. One allocation shared by both stage
+// sizes (kSG = 4, or 2 when D / 256 is not a multiple of 4).
+constexpr int kStageBytes = 2 * (kRows + kQueries) * 128;  // two 4-group stages
+__device__ __forceinline__ char* stage_lds() {
+  __shared__ __attribute__((aligned(16))) char buf[kStageBytes];
+  return buf;
+}
+// library indices of each wave's 128 rows of a block, two blocks in flight
+__device__ __forceinline__ uint32_t* orig_lds() {
+  __shared__ __attribute__((aligned(16))) uint32_t buf[2 * WR * WQ * TR * 32];
+  return buf;
+}
+
+template <int F, int kSG>
+__device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
     uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
     uint64_t* __restrict__ keys)
 {
   constexpr int MR = kRows, NQ = kQueries;
+  constexpr int kRowBytes = kSG * 32;    // bytes of a row per stage
+  constexpr int kP = 2 * kSG;            // 16-byte pieces per row and stage
+  constexpr int kRPB = 64 / (8 * kSG);   // rows between repeats of the bank pattern
+  constexpr int kRPI = 64 / kP;          // rows per direct-load instruction
+  constexpr int kLI = 32 / kRPI;         // instructions per wave and operand (32 rows)
+  constexpr int kBuf = (MR + NQ) * kRowBytes;
+  static_assert(2 * kBuf <= kStageBytes, "stage buffers");
   const uint32_t D = words * 32;
   const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w % WR, wq = w / WR;
   const int h = l >> 5;
+  char* const lds = stage_lds();
+  uint32_t* const s_orig = orig_lds();
 
   // query columns of this lane (B rows and epilogue columns coincide)
-  const uint32_t* qrow[TQ];
   uint32_t qlo[TQ], qhi[TQ], qid[TQ];
   uint64_t bk[TQ];
   bool qok[TQ];
+  float need[TQ];
 #pragma unroll
   for (int j = 0; j < TQ; ++j) {
     const int64_t qs = tile * NQ + wq * TQ * 32 + j * 32 + (l & 31);
@@ -106,37 +134,121 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     qid[j] = qok[j] ? qperm[qs] : qperm[nq - 1];
     qlo[j] = qok[j] ? (uint32_t)lo[qid[j]] : 0u;
     qhi[j] = qok[j] ? (uint32_t)hi[qid[j]] : 0u;
-    qrow[j] = q_hv + (size_t)qid[j] * words + 4 * h;
     bk[j] = ~0ull;
+    // Dot product a row must reach to matter: that of the query's best so
+    // far (from other workgroups; equal dots still matter for the index
+    // rule). Absent queries never update.
+    const uint64_t k0 = qok[j] ? keys[qid[j]] : 0ull;
+    need[j] = !qok[j] ? INFINITY
+              : k0 == ~0ull ? -INFINITY
+                            : (float)((int)D - 2 * (int)(uint32_t)(k0 >> 32));
   }
-  const uint32_t G = words / 8;
+  // query rows this lane moves into LDS: rows w * 32 + x * kRPI + l / kP
+  const char* qld[kLI];
+#pragma unroll
+  for (int x = 0; x < kLI; ++x) {
+    const int64_t qs = tile * NQ + w * 32 + x * kRPI + l / kP;
+    const uint32_t qi = qs < nq ? qperm[qs] : qperm[nq - 1];
+    qld[x] = (const char*)(q_hv + (size_t)qi * words);
+  }
+  // Consume these loads here: the compiler does not see the direct loads
+  // below, and a wait of its own placed after them would drain them too.
+#pragma unroll
+  for (int j = 0; j < TQ; ++j)
+    asm volatile("" : "+v"(qlo[j]), "+v"(qhi[j]), "+v"(qid[j]), "+v"(need[j]));
+#pragma unroll
+  for (int x = 0; x < kLI; ++x) asm volatile("" : "+v"(qld[x]));
+
+  const uint32_t SPB = words / (8 * kSG);  // stages per block
   const uint32_t nblk = (b - a + MR - 1) / MR;
+  const uint32_t total = nblk * SPB;
   uint32_t sel = F == 0 ? 0x80808080u : 0x88888888u, one = F == 0 ? 0x38383838u : 0x22222222u;
   asm volatile("" : "+v"(sel), "+v"(one));  // keep both in VGPRs
 
-  for (uint32_t blk = 0; blk < nblk; ++blk) {
-    const uint32_t* arow[TR];
+  // piece loaded by this lane in instruction x: LDS position l % kP of row
+  // w * 32 + x * kRPI + l / kP holds piece position ^ f(row)
+  auto lpos = [&](int x) {
+    const uint32_t row = (uint32_t)(w * 32 + x * kRPI + l / kP);
+    return (uint32_t)(l % kP) ^ ((row / kRPB) % kP);
+  };
+  // Stage S into buffer S % 2: library rows (clamped to the chunk's last
+  // row) and query rows, preceded at a block's first stage by the block's
+  // library indices. A direct load writes lane l's 16 (4) bytes to M0 + 16 l
+  // (M0 + 4 l). 2 kLI loads per stage, 2 more at a block's first stage.
+  auto issue = [&](uint32_t S) {
+    const uint32_t B = S / SPB, sp = S % SPB;
+    const uint32_t rb = a + B * MR;
+    const uint32_t lim = b - 1u - rb;
+    if (sp == 0) {
 #pragma unroll
-    for (int i = 0; i < TR; ++i) {
-      const uint32_t row = a + blk * MR + wr * TR * 32 + i * 32 + (l & 31);
-      arow[i] = lib + (size_t)min(row, b - 1u) * words + 4 * h;
+      for (int x = 0; x < 2; ++x) {
+        const uint32_t voff = (rb + wr * TR * 32 + 64 * x + l) * 4u;  // orig is padded
+        const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(s_orig + ((B & 1) * WR * WQ + w) * TR * 32 + 64 * x));
+        asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1"
+                     :
+                     : "v"(voff), "s"(orig), "s"(m0)
+                     : "memory", "m0");
+      }
     }
-    v16f acc[TR][TQ];
+    char* const sA = lds + (S & 1) * kBuf;
+    char* const sB = sA + MR * kRowBytes;
+    const char* gA = (const char*)(lib + (size_t)rb * words);  // uniform
 #pragma unroll
-    for (int i = 0; i < TR; ++i)
+    for (int x = 0; x < kLI; ++x) {
+      const uint32_t row = (uint32_t)(w * 32 + x * kRPI + l / kP);
+      const uint32_t voff = min(row, lim) * words * 4u + sp * kRowBytes + lpos(x) * 16u;
+      const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+          (uint32_t)(uintptr_t)(sA + (w * 32 + x * kRPI) * kRowBytes));
+      asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                   :
+                   : "v"(voff), "s"(gA), "s"(m0)
+                   : "memory", "m0");
+    }
 #pragma unroll
-      for (int j = 0; j < TQ; ++j) acc[i][j] = v16f{0};
-    // packed words of two groups in flight: x* is consumed while y* loads
-    uint4 xa[TR], xb[TQ], ya[TR], yb[TQ];
-    auto load = [&](uint32_t g, uint4 (&da)[TR], uint4 (&db)[TQ]) {
-      const uint32_t off = (g < G ? g : G - 1) * 8;
+    for (int x = 0; x < kLI; ++x) {
+      const char* src = qld[x] + sp * kRowBytes + lpos(x) * 16u;
+      const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+          (uint32_t)(uintptr_t)(sB + (w * 32 + x * kRPI) * kRowBytes));
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                   :
+                   : "v"(src), "s"(m0)
+                   : "memory", "m0");
+    }
+  };
+
+  // Operand reads: row (l & 31) of a 32-row tile, piece 2 g + h (k half h of
+  // group g takes words 4h .. 4h + 3 of the group's 8 words, the same for A
+  // and B). Every tile of a wave starts at a multiple of 32 rows, so the
+  // position of the piece depends on the lane only.
+  const uint32_t r31 = (uint32_t)(l & 31);
+  uint32_t roff[kSG];
 #pragma unroll
-      for (int i = 0; i < TR; ++i) da[i] = *(const uint4*)(arow[i] + off);
+  for (int g = 0; g < kSG; ++g)
+    roff[g] = r31 * kRowBytes + 16u * ((uint32_t)(2 * g + h) ^ ((r31 / kRPB) % kP));
+
+  issue(0);
+  v16f acc[TR][TQ];
+  for (uint32_t S = 0; S < total; ++S) {
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // this wave's loads of stage S
+    __syncthreads();  // every wave's loads landed; stage S - 1 is fully read
+    if (S + 1 < total) issue(S + 1);
+    const uint32_t sp = S % SPB;
+    if (sp == 0) {
 #pragma unroll
-      for (int j = 0; j < TQ; ++j) db[j] = *(const uint4*)(qrow[j] + off);
-      __builtin_amdgcn_sched_barrier(0);  // issued before the group's work
-    };
-    auto group = [&](const uint4 (&ca)[TR], const uint4 (&cb)[TQ]) {
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TQ; ++j) acc[i][j] = v16f{0};
+    }
+    const char* bufA = lds + (S & 1) * kBuf + wr * TR * 32 * kRowBytes;
+    const char* bufB = lds + (S & 1) * kBuf + MR * kRowBytes + wq * TQ * 32 * kRowBytes;
+#pragma unroll
+    for (int g = 0; g < kSG; ++g) {
+      uint4 ca[TR], cb[TQ];
+#pragma unroll
+      for (int i = 0; i < TR; ++i) ca[i] = *(const uint4*)(bufA + i * 32 * kRowBytes + roff[g]);
+#pragma unroll
+      for (int j = 0; j < TQ; ++j) cb[j] = *(const uint4*)(bufB + j * 32 * kRowBytes + roff[g]);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         v8i bv[TQ];
@@ -155,37 +267,78 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
                                                                          0, 0, 0, 0);
         }
       }
-    };
-    load(0, xa, xb);
-    for (uint32_t g = 0; g < G; g += 2) {  // G = D / 256 is even
-      load(g + 1, ya, yb);
-      group(xa, xb);
-      load(g + 2, xa, xb);
-      group(ya, yb);
     }
+    if (sp != SPB - 1) continue;
+
+    // Epilogue of block blk. Accumulator register r of tile (i, j) holds row
+    // base + 32 i + 8 (r / 4) + 4 (l / 32) + r % 4 and query column j; the
+    // block's library indices are in LDS (their load is older than stage S's).
+    const uint32_t blk = S / SPB;
     const uint32_t base = a + blk * MR + wr * TR * 32;
+    const uint32_t* so = s_orig + ((blk & 1) * WR * WQ + w) * TR * 32 + 4 * (l >> 5);
+    bool inner = base + TR * 32 <= b;
 #pragma unroll
-    for (int i = 0; i < TR; ++i) {
+    for (int j = 0; j < TQ; ++j)
+      inner = inner && (!qok[j] || (qlo[j] <= base && base + TR * 32 <= qhi[j]));
+    if (__ballot(!inner) == 0) {
+      // every row of the wave is a candidate of every query column: the
+      // column maximum decides, and only a maximum that reaches the best so
+      // far looks up library indices
 #pragma unroll
-      for (int rg = 0; rg < 4; ++rg) {
-        const uint32_t g0 = base + i * 32 + 8 * rg + 4 * (l >> 5);
-        const uint4 o4 = *(const uint4*)(orig + g0);  // orig is padded past the end
-        const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
+      for (int j = 0; j < TQ; ++j) {
+        float m = acc[0][j][0];
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const uint32_t g = g0 + r4;
+        for (int i = 0; i < TR; ++i)
 #pragma unroll
-          for (int j = 0; j < TQ; ++j) {
-            const int dot = (int)acc[i][j][4 * rg + r4];
-            const uint32_t d = (uint32_t)((int)D - dot) >> 1;
-            const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
-            const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;
-            bk[j] = key < bk[j] ? key : bk[j];
+          for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[i][j][r]);
+        if (m >= need[j]) {
+          uint32_t o_min = ~0u;
+#pragma unroll
+          for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+              const uint4 o4 = *(const uint4*)(so + i * 32 + 8 * rg);
+              const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+              for (int r4 = 0; r4 < 4; ++r4)
+                if (acc[i][j][4 * rg + r4] == m) o_min = min(o_min, ov[r4]);
+            }
+          const uint32_t d = (uint32_t)((int)D - (int)m) >> 1;
+          const uint64_t key = ((uint64_t)d << 32) | o_min;
+          bk[j] = key < bk[j] ? key : bk[j];
+          need[j] = m;
+        }
+      }
+    } else {
+      // window or chunk edge inside the wave's rows: per-row masks
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) {
+          const uint32_t g0 = base + i * 32 + 8 * rg + 4 * (l >> 5);
+          const uint4 o4 = *(const uint4*)(so + i * 32 + 8 * rg);
+          const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const uint32_t g = g0 + r4;
+#pragma unroll
+            for (int j = 0; j < TQ; ++j) {
+              const int dot = (int)acc[i][j][4 * rg + r4];
+              const uint32_t d = (uint32_t)((int)D - dot) >> 1;
+              const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
+              const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;
+              bk[j] = key < bk[j] ? key : bk[j];
+            }
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < TQ; ++j)
+        if (bk[j] != ~0ull)
+          need[j] = fmaxf(need[j], (float)((int)D - 2 * (int)(uint32_t)(bk[j] >> 32)));
     }
   }
+  __syncthreads();  // LDS is free again when the caller starts another tile
 #pragma unroll
   for (int j = 0; j < TQ; ++j) {
     const uint64_t k = bk[j];
@@ -196,6 +349,19 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
   }
 }
 
+// 4-group stages when D / 256 is a multiple of 4, else 2-group stages
+template <int F>
+__device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
+    const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
+    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
+    uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
+    uint64_t* __restrict__ keys)
+{
+  if (words % 32 == 0)
+    tile_rows_staged<F, 4>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, keys);
+  else
+    tile_rows_staged<F, 2>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, keys);
+}
 
 }  // namespace mfd
 }  // namespace homs
