@@ -46,7 +46,8 @@ MFMA_F4_PEAK_TOPS = 10100.0  # dense fp4 (and fp6) matrix peak of MI355X, TFLOP/
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
 MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
-                    ("mfma_fp8", "4bb9ca345dad1002"): 8.123e11}
+                    ("mfma_fp4", "2fb353cada6e0c98"): 2.618e11,
+                    ("mfma_fp8", "2fb353cada6e0c98"): 2.790e11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
@@ -91,7 +92,7 @@ def main():
                     help="queries in the oracle's timed sample (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baseline (for profiler runs)")
-    ap.add_argument("--engine", default="mfma_fp8", choices=list(ENGINE_SOURCES),
+    ap.add_argument("--engine", default="mfma_fp4", choices=list(ENGINE_SOURCES),
                     help="search engine of the timed step (all are bit-exact)")
     ap.add_argument("--skip-mfma", action="store_true",
                     help="time only the step's engine (no side-by-side engine timings)")
@@ -439,18 +440,20 @@ def bench_learned(args, w, dev):
     ctx.profile_enable(True)
     ctx.profile_read()
     ex = {}
-    for name, engine in (("popcount", h.ENGINE_POPCOUNT), ("mfma_fp8", h.ENGINE_MFMA_F8)):
+    for name, engine in (("popcount", h.ENGINE_POPCOUNT), ("mfma_fp8", h.ENGINE_MFMA_F8),
+                         ("mfma_fp4", h.ENGINE_MFMA_F4)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e_idx, e_dist = ctx.search_window(q_hv, q_pmz, q_ch, h.TOL_DA, 500.0, engine)
         torch.cuda.synchronize()
         ex[name] = time.perf_counter() - t0
     ctx.profile_read()
-    log(f"exhaustive search: popcount {ex['popcount']:.2f}s, fp8 {ex['mfma_fp8']:.2f}s")
+    log(f"exhaustive search: popcount {ex['popcount']:.2f}s, fp8 {ex['mfma_fp8']:.2f}s, "
+        f"fp4 {ex['mfma_fp4']:.2f}s")
 
     # training pairs: exact top-1 of the training queries, batched in m/z order
     t0 = time.perf_counter()
-    t_idx, _ = ctx.search_window(t_hv, t_pmz, t_ch, h.TOL_DA, 500.0, h.ENGINE_MFMA_F8)
+    t_idx, _ = ctx.search_window(t_hv, t_pmz, t_ch, h.TOL_DA, 500.0, h.ENGINE_MFMA_F4)
     lib_rows = ctx.library_export()
     order = torch.from_numpy(np.lexsort((tr.pmz, tr.charge))).to(dev)
     order = order[t_idx[order] >= 0]
@@ -530,6 +533,7 @@ def bench_learned(args, w, dev):
         "top1_agreement": agree, "top1_agreement_untrained": agree0, "fallback_rate": fbr,
         "exhaustive_s": ex, "speedup_vs_popcount": ex["popcount"] / step_s,
         "speedup_vs_mfma_fp8": ex["mfma_fp8"] / step_s,
+        "speedup_vs_mfma_fp4": ex["mfma_fp4"] / step_s,
         "train_s": train_s, "train_steps": len(losses), "label_s": label_s,
         "embed_library_s": embed_lib_s,
         "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0,

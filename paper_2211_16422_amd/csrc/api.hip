@@ -795,8 +795,8 @@ homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_h
     const uint32_t narrows[] = {256, 1024, 4096};
     const uint32_t groups[] = {16, 32, 64};
     const uint32_t engines[] = {HOMS_ENGINE_POPCOUNT, HOMS_ENGINE_MFMA_F8, HOMS_ENGINE_MFMA_F4};
-    auto sweep = [&](auto set, const uint32_t* vals, int n) {
-        for (int i = 0; i < n && st == HOMS_OK; ++i) {
+    auto sweep = [&](auto set, const auto& vals) {
+        for (size_t i = 0; i < sizeof(vals) / sizeof(vals[0]) && st == HOMS_OK; ++i) {
             homs::BatchedConfig cand = cur;
             set(cand, vals[i]);
             double ms = 0.0;
@@ -807,11 +807,11 @@ homs_status homs_autotune_batched(homs_ctx* c, int64_t nq, const uint32_t* d_q_h
             }
         }
     };
-    sweep([](homs::BatchedConfig& b, uint32_t v) { b.engine = (int32_t)v; }, engines, 2);
-    sweep([](homs::BatchedConfig& b, uint32_t v) { b.chunk_rows = v; }, chunks, 4);
-    sweep([](homs::BatchedConfig& b, uint32_t v) { b.grid = v; }, grids, 4);
-    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_max = v; }, narrows, 3);
-    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_group = v; }, groups, 3);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.engine = (int32_t)v; }, engines);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.chunk_rows = v; }, chunks);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.grid = v; }, grids);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_max = v; }, narrows);
+    sweep([](homs::BatchedConfig& b, uint32_t v) { b.narrow_group = v; }, groups);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     c->prof.on = prof;
