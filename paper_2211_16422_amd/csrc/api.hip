@@ -166,6 +166,7 @@ struct SearchScratch {
     uint32_t* qp_b;
     int64_t* tile_lo;
     int64_t* tile_hi;
+    int32_t* qoff;  // per-query constants of the fp4 engine
     void* sort_tmp;
     size_t sort_bytes;
 };
@@ -174,7 +175,7 @@ size_t search_scratch_bytes(int64_t nq, int tile)
 {
     const int64_t nt = (nq + tile - 1) / tile;
     return 2 * al(nq * 8) + al(nq * 8) + 2 * al(nq * 8) + 2 * al(nq * 4) + 2 * al(nt * 8) +
-           homs::query_sort_temp_bytes(nq);
+           al(nq * 4) + homs::query_sort_temp_bytes(nq);
 }
 
 SearchScratch carve(void* base, int64_t nq, int tile)
@@ -200,6 +201,8 @@ SearchScratch carve(void* base, int64_t nq, int tile)
     p += al(nt * 8);
     s.tile_hi = (int64_t*)p;
     p += al(nt * 8);
+    s.qoff = (int32_t*)p;
+    p += al(nq * 4);
     s.sort_tmp = p;
     s.sort_bytes = homs::query_sort_temp_bytes(nq);
     return s;
@@ -572,7 +575,8 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
                                                : engine == HOMS_ENGINE_MFMA_F8 ? 1
                                                                                : 2,
                                             nq, d_q_hv,
-                                            qperm, w.lo, w.hi, w.tile_lo, w.tile_hi, w.keys, s),
+                                            qperm, w.lo, w.hi, w.tile_lo, w.tile_hi, w.qoff, w.keys,
+                                            s),
                 "MFMA search kernel");
     hipEvent_t e2 = prof_mark(c, s);
     HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");

@@ -142,9 +142,12 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
 // search_mfma.hip (fmt 0: int8, 1: fp8 e4m3, 2: fp4 e2m1)
 int search_mfma_tile();
 int64_t search_mfma_row_pad();  // rows of padding the library's orig array needs
+// qoff: workspace of nq int32 (the fp4 form's per-query constants)
 hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint32_t* q_hv,
                               const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
-                              const int64_t* tile_lo, const int64_t* tile_hi, uint64_t* keys,
-                              hipStream_t s);
+                              const int64_t* tile_lo, const int64_t* tile_hi, int32_t* qoff,
+                              uint64_t* keys, hipStream_t s);
+hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                    int32_t* qoff, hipStream_t s);
 
 }  // namespace homs

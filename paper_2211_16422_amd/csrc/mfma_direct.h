@@ -7,12 +7,21 @@
 // owning 128 rows x 64 queries of a 256 x 256 block), D a multiple of 512,
 // and an orig array padded by 256 entries past the library.
 //
-// With bit 0 = +1 and bit 1 = -1, H = (D - <x, y>) / 2 and <x, y> is exact in
-// fp32 (integers of magnitude <= D), so the distances equal the popcount
-// ones bit for bit. +-1 is exact in both element formats (fp8 e4m3 0x38 /
-// 0xB8, fp4 e2m1 0x2 / 0xA), and so is every product. fp4 operands take half
-// the register bytes and half the matrix cycles of fp8 ones for the same 64
-// components.
+// fp8: with bit 0 = +1 and bit 1 = -1 on both sides, H = (D - <x, y>) / 2,
+// and <x, y> is an integer of magnitude <= D, exact in fp32.
+//
+// fp4 (half the operand bytes and half the matrix cycles of fp8): the query
+// side is symmetric, component c of class m = c mod 4 being (-1)^b beta_m
+// with beta = (4, 2, 1, 1); the library side is not, being u_m + a delta_m
+// with (u, u + delta) = (-1, -1.5), (-0, -1), (-0, -2), (+1, -1). Every class
+// has delta_m beta_m = -2, so the dot product is sum over classes of
+// u beta (n - 2|b|) + 2|b| - 2H: a per-query constant Q minus 2H, with
+// Q = -3D/4 + 10|b|_0 + 2|b|_1 + 2|b|_2 (|b|_m: the query's set bits of class
+// m). Every product is an integer (+-1, +-2, +-4, +-6 or 0) and every sum
+// is below 2^15, so H = (Q - <x, y>) / 2 holds exactly. The point of the
+// asymmetry: a library-side bit stays where it is in its word (one v_bfi_b32
+// per 8 components, no shift), which takes 3 of every 7 expansion operations
+// off the side that is expanded twice as often.
 //
 // Data movement: the packed bits of the block's 256 library rows and 256
 // query rows move into LDS in stages of 4 groups (1,024 components, one
@@ -59,30 +68,37 @@ __device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t
   return o;
 }
 
-// 32 packed bits -> 32 fp4 e2m1 nibbles of +-1.0 (0x2 / 0xA) in the low four
-// dwords of the operand (the fp4 form reads no others). Nibble j of dword m
-// carries bit m + 4 j in its sign position: one shift and one bit insert per
-// 8 components, the same order for both operands.
-__device__ __forceinline__ v8i expand_pm1_fp4(uint32_t w, uint32_t sel, uint32_t one) {
+// 32 packed bits -> 32 fp4 e2m1 nibbles in the low four dwords of the operand
+// (the fp4 form reads no others); nibble j of dword m is component m + 4 j of
+// the word, the same order on both sides. Query side: the bit moves to the
+// sign position (one shift and one bit insert per dword) of magnitude
+// beta_m = 4, 2, 1, 1 (mag[m] = 0x66666666, 0x44444444, 0x22222222,
+// 0x22222222). Library side: the bit stays in place (one bit insert per
+// dword) and selects between u_m and u_m + delta_m (sel[m] = 0x11111111 << m,
+// base[m] = 0xAAAAAAAA, 0x88888888, 0x88888888, 0x22222222).
+struct Fp4Consts {
+  uint32_t c11, c22, c44, c88, cAA, c66;  // kept in VGPRs (VOP3 takes no literals)
+};
+__device__ __forceinline__ uint32_t bfi(uint32_t sel, uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(y));
+  return r;
+}
+__device__ __forceinline__ v8i expand_query_fp4(uint32_t w, const Fp4Consts& k) {
   v8i o = v8i{0};
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const uint32_t x = w << (3 - m);
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(one));
-    o[m] = (int)r;
-  }
+  o[0] = (int)bfi(k.c88, w << 3, k.c66);
+  o[1] = (int)bfi(k.c88, w << 2, k.c44);
+  o[2] = (int)bfi(k.c88, w << 1, k.c22);
+  o[3] = (int)bfi(k.c88, w, k.c22);
   return o;
 }
-
-// element format code of the f8f6f4 matrix instruction: 0 = fp8 e4m3, 4 = fp4 e2m1
-template <int F>
-__device__ __forceinline__ v8i expand_pm1(uint32_t w, uint32_t sel, uint32_t one) {
-  static_assert(F == 0 || F == 4, "fp8 e4m3 or fp4 e2m1");
-  if constexpr (F == 0)
-    return expand_pm1_fp8(w, sel, one);
-  else
-    return expand_pm1_fp4(w, sel, one);
+__device__ __forceinline__ v8i expand_lib_fp4(uint32_t w, const Fp4Consts& k) {
+  v8i o = v8i{0};
+  o[0] = (int)bfi(k.c11, w, k.cAA);
+  o[1] = (int)bfi(k.c22, w, k.c88);
+  o[2] = (int)bfi(k.c44, w, k.c88);
+  o[3] = (int)bfi(k.c88, w, k.c22);
+  return o;
 }
 
 // Stage buffers: per stage, 256 library rows and 256 query rows of kSG * 32
@@ -101,12 +117,13 @@ __device__ __forceinline__ uint32_t* orig_lds() {
   return buf;
 }
 
+// qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8)
 template <int F, int kSG>
 __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
     uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
-    uint64_t* __restrict__ keys)
+    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
 {
   constexpr int MR = kRows, NQ = kQueries;
   constexpr int kRowBytes = kSG * 32;    // bytes of a row per stage
@@ -122,8 +139,10 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   char* const lds = stage_lds();
   uint32_t* const s_orig = orig_lds();
 
-  // query columns of this lane (B rows and epilogue columns coincide)
+  // query columns of this lane (B rows and epilogue columns coincide);
+  // distance = (Q - dot) / 2 with Q = D (fp8) or the query's constant (fp4)
   uint32_t qlo[TQ], qhi[TQ], qid[TQ];
+  int Q[TQ];
   uint64_t bk[TQ];
   bool qok[TQ];
   float need[TQ];
@@ -134,6 +153,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     qid[j] = qok[j] ? qperm[qs] : qperm[nq - 1];
     qlo[j] = qok[j] ? (uint32_t)lo[qid[j]] : 0u;
     qhi[j] = qok[j] ? (uint32_t)hi[qid[j]] : 0u;
+    Q[j] = F == 4 ? qoff[qid[j]] : (int)D;
     bk[j] = ~0ull;
     // Dot product a row must reach to matter: that of the query's best so
     // far (from other workgroups; equal dots still matter for the index
@@ -141,7 +161,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint64_t k0 = qok[j] ? keys[qid[j]] : 0ull;
     need[j] = !qok[j] ? INFINITY
               : k0 == ~0ull ? -INFINITY
-                            : (float)((int)D - 2 * (int)(uint32_t)(k0 >> 32));
+                            : (float)(Q[j] - 2 * (int)(uint32_t)(k0 >> 32));
   }
   // query rows this lane moves into LDS: rows w * 32 + x * kRPI + l / kP
   const char* qld[kLI];
@@ -155,15 +175,20 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   // below, and a wait of its own placed after them would drain them too.
 #pragma unroll
   for (int j = 0; j < TQ; ++j)
-    asm volatile("" : "+v"(qlo[j]), "+v"(qhi[j]), "+v"(qid[j]), "+v"(need[j]));
+    asm volatile("" : "+v"(qlo[j]), "+v"(qhi[j]), "+v"(qid[j]), "+v"(need[j]), "+v"(Q[j]));
 #pragma unroll
   for (int x = 0; x < kLI; ++x) asm volatile("" : "+v"(qld[x]));
 
   const uint32_t SPB = words / (8 * kSG);  // stages per block
   const uint32_t nblk = (b - a + MR - 1) / MR;
   const uint32_t total = nblk * SPB;
-  uint32_t sel = F == 0 ? 0x80808080u : 0x88888888u, one = F == 0 ? 0x38383838u : 0x22222222u;
-  asm volatile("" : "+v"(sel), "+v"(one));  // keep both in VGPRs
+  uint32_t sel = 0x80808080u, one = 0x38383838u;  // fp8
+  Fp4Consts k4{0x11111111u, 0x22222222u, 0x44444444u, 0x88888888u, 0xAAAAAAAAu, 0x66666666u};
+  if constexpr (F == 0)
+    asm volatile("" : "+v"(sel), "+v"(one));  // keep in VGPRs
+  else
+    asm volatile("" : "+v"(k4.c11), "+v"(k4.c22), "+v"(k4.c44), "+v"(k4.c88), "+v"(k4.cAA),
+                 "+v"(k4.c66));
 
   // piece loaded by this lane in instruction x: LDS position l % kP of row
   // w * 32 + x * kRPI + l / kP holds piece position ^ f(row)
@@ -255,12 +280,19 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 #pragma unroll
         for (int j = 0; j < TQ; ++j) {
           const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
-          bv[j] = expand_pm1<F>(x, sel, one);
+          if constexpr (F == 0)
+            bv[j] = expand_pm1_fp8(x, sel, one);
+          else
+            bv[j] = expand_query_fp4(x, k4);
         }
 #pragma unroll
         for (int i = 0; i < TR; ++i) {
           const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
-          const v8i av = expand_pm1<F>(x, sel, one);
+          v8i av;
+          if constexpr (F == 0)
+            av = expand_pm1_fp8(x, sel, one);
+          else
+            av = expand_lib_fp4(x, k4);
 #pragma unroll
           for (int j = 0; j < TQ; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], F, F,
@@ -303,7 +335,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
               for (int r4 = 0; r4 < 4; ++r4)
                 if (acc[i][j][4 * rg + r4] == m) o_min = min(o_min, ov[r4]);
             }
-          const uint32_t d = (uint32_t)((int)D - (int)m) >> 1;
+          const uint32_t d = (uint32_t)(Q[j] - (int)m) >> 1;
           const uint64_t key = ((uint64_t)d << 32) | o_min;
           bk[j] = key < bk[j] ? key : bk[j];
           need[j] = m;
@@ -324,7 +356,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 #pragma unroll
             for (int j = 0; j < TQ; ++j) {
               const int dot = (int)acc[i][j][4 * rg + r4];
-              const uint32_t d = (uint32_t)((int)D - dot) >> 1;
+              const uint32_t d = (uint32_t)(Q[j] - dot) >> 1;
               const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
               const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;
               bk[j] = key < bk[j] ? key : bk[j];
@@ -335,7 +367,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 #pragma unroll
       for (int j = 0; j < TQ; ++j)
         if (bk[j] != ~0ull)
-          need[j] = fmaxf(need[j], (float)((int)D - 2 * (int)(uint32_t)(bk[j] >> 32)));
+          need[j] = fmaxf(need[j], (float)(Q[j] - 2 * (int)(uint32_t)(bk[j] >> 32)));
     }
   }
   __syncthreads();  // LDS is free again when the caller starts another tile
@@ -355,12 +387,12 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
     uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
-    uint64_t* __restrict__ keys)
+    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
 {
   if (words % 32 == 0)
-    tile_rows_staged<F, 4>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, keys);
+    tile_rows_staged<F, 4>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff, keys);
   else
-    tile_rows_staged<F, 2>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, keys);
+    tile_rows_staged<F, 2>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff, keys);
 }
 
 }  // namespace mfd

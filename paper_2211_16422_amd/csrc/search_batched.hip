@@ -198,7 +198,8 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                          const uint32_t* __restrict__ tile_item, int64_t max_tiles,
                          uint32_t chunk_rows, uint32_t narrow_group, Plan* __restrict__ plan,
                          const uint32_t* __restrict__ lib_hv,
-                         const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
+                         const uint32_t* __restrict__ lib_orig, const int32_t* __restrict__ qoff,
+                         uint64_t* __restrict__ keys)
 {
     static_assert(popc::kTile == mfd::kQueries, "all engines use 256-query tiles");
     constexpr int kFormat = ENGINE == HOMS_ENGINE_MFMA_F4 ? 4 : 0;  // f8f6f4 element format
@@ -232,7 +233,8 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                                              (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
                 else
                     mfd::tile_rows<kFormat>(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
-                                            (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, keys);
+                                            (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, qoff,
+                                            keys);
             }
         } else {
             const int64_t first = (int64_t)n_wide + (int64_t)(item - wide_items) * narrow_group;
@@ -256,7 +258,8 @@ size_t batched_scratch_bytes(int64_t nq)
     const int64_t max_tiles = (nq + popc::kTile - 1) / popc::kTile + 1;
     const int64_t scan_blocks = (kBuckets + kScanBlock - 1) / kScanBlock;
     return 2 * al(nq * 8) + al(nq * 8) + 2 * al(nq * 4) + al(kBuckets * 4) +
-           al(scan_blocks * 4) + 2 * al(max_tiles * 8) + al(max_tiles * 4) + al(sizeof(Plan));
+           al(scan_blocks * 4) + 2 * al(max_tiles * 8) + al(max_tiles * 4) + al(nq * 4) +
+           al(sizeof(Plan));
 }
 
 hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, void* scratch,
@@ -289,6 +292,8 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
     p += al(max_tiles * 8);
     uint32_t* tile_item = (uint32_t*)p;
     p += al(max_tiles * 4);
+    int32_t* qoff = (int32_t*)p;  // per-query constants of the fp4 engine
+    p += al(nq * 4);
     Plan* plan = (Plan*)p;
 
     hipError_t e = launch_window_bounds(c, nq, q_pmz, q_charge, HOMS_TOL_DA, 0.0, kinds, values,
@@ -305,18 +310,21 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
     plan_kernel<<<1, 1024, 0, s>>>(nq, hist, order, lo, hi, cfg.chunk_rows, cfg.narrow_group,
                                    max_tiles, tile_lo, tile_hi, tile_item, plan);
     fill_u64_kernel<<<blocks_for(nq), kThreads, 0, s>>>(keys, nq, ~0ull);
-    if (cfg.engine == HOMS_ENGINE_MFMA_F8)
+    if (cfg.engine == HOMS_ENGINE_MFMA_F8) {
         persistent_search_kernel<HOMS_ENGINE_MFMA_F8><<<cfg.grid, mfd::kThreads, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
-    else if (cfg.engine == HOMS_ENGINE_MFMA_F4)
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, keys);
+    } else if (cfg.engine == HOMS_ENGINE_MFMA_F4) {
+        e = launch_fp4_query_offsets(c, nq, q_hv, qoff, s);
+        if (e != hipSuccess) return e;
         persistent_search_kernel<HOMS_ENGINE_MFMA_F4><<<cfg.grid, mfd::kThreads, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
-    else
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, qoff, keys);
+    } else {
         persistent_search_kernel<HOMS_ENGINE_POPCOUNT><<<cfg.grid, popc::kTile, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, keys);
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, keys);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(nq, keys, out_idx, out_dist, s);

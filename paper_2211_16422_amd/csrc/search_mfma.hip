@@ -227,8 +227,9 @@ __global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t 
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
-    const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig, uint64_t* __restrict__ keys,
-    int64_t chunk, int64_t n_tiles, int64_t chunk_patches, int64_t patches)
+    const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
+    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys, int64_t chunk, int64_t n_tiles,
+    int64_t chunk_patches, int64_t patches)
 {
   const int64_t wg = blockIdx.x;
   const int64_t slot = wg / kXcds;  // position in this XCD's sequence
@@ -242,7 +243,26 @@ __global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t 
   const int64_t b64 = min(cidx * chunk + chunk, thi[tile]);
   if (a64 >= b64) return;
   mfd::tile_rows<F>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64, (uint32_t)b64, lib,
-                    orig, keys);
+                    orig, qoff, keys);
+}
+
+// The fp4 form's per-query constant Q = -3D/4 + 10 |b|_0 + 2 |b|_1 + 2 |b|_2,
+// |b|_m the query's set bits at components of class m (component mod 4), one
+// wave per query.
+__global__ __launch_bounds__(256) void fp4_query_offsets_kernel(int64_t nq, uint32_t words,
+    const uint32_t* __restrict__ q_hv, int32_t* __restrict__ qoff)
+{
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (q >= nq) return;
+  const uint32_t* row = q_hv + (size_t)q * words;
+  int s = 0;
+  for (uint32_t i = l; i < words; i += 64) {
+    const uint32_t w = row[i];
+    s += 10 * __builtin_popcount(w & 0x11111111u) + 2 * __builtin_popcount(w & 0x66666666u);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (l == 0) qoff[q] = s - (int)(3 * words * 8);
 }
 
 constexpr int kMfWR = 2, kMfWQ = 4, kMfTR = 4, kMfTQ = 2;
@@ -254,10 +274,18 @@ constexpr int64_t kMfChunk = 4096;
 int search_mfma_tile() { return kMfQueries; }
 int64_t search_mfma_row_pad() { return kMfWR * kMfTR * 32; }
 
+hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
+                                    int32_t* qoff, hipStream_t s)
+{
+    if (nq <= 0) return hipSuccess;
+    fp4_query_offsets_kernel<<<(uint32_t)((nq + 3) / 4), 256, 0, s>>>(nq, c->words, q_hv, qoff);
+    return hipGetLastError();
+}
+
 hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint32_t* q_hv,
                               const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
-                              const int64_t* tile_lo, const int64_t* tile_hi, uint64_t* keys,
-                              hipStream_t s)
+                              const int64_t* tile_lo, const int64_t* tile_hi, int32_t* qoff,
+                              uint64_t* keys, hipStream_t s)
 {
     const int64_t n_tiles = (nq + kMfQueries - 1) / kMfQueries;
     if (n_tiles <= 0 || c->lib.n <= 0) return hipSuccess;
@@ -275,14 +303,17 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
         // whole rounds of kXcds patches, so every XCD's sequence is complete
         const int64_t blocks = (patches + kXcds - 1) / kXcds * kXcds * kPatch;
         if (blocks > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-        if (fmt == 1)
+        if (fmt == 1) {
             mfma_direct_kernel<0><<<(uint32_t)blocks, block, 0, s>>>(
-                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
-                kMfChunk, n_tiles, chunk_patches, patches);
-        else
+                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig,
+                nullptr, keys, kMfChunk, n_tiles, chunk_patches, patches);
+        } else {
+            const hipError_t e = launch_fp4_query_offsets(c, nq, q_hv, qoff, s);
+            if (e != hipSuccess) return e;
             mfma_direct_kernel<4><<<(uint32_t)blocks, block, 0, s>>>(
-                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig, keys,
-                kMfChunk, n_tiles, chunk_patches, patches);
+                c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig,
+                qoff, keys, kMfChunk, n_tiles, chunk_patches, patches);
+        }
     }
     return hipGetLastError();
 }
