@@ -189,6 +189,8 @@ WORKLOADS = {
     "tiny": Workload("tiny", 2000, 200, 2048),
     # plain method at library scale: the throughput workload
     "large": Workload("large", 1_000_000, 100_000, 8192),
+    # the same data in higher-capacity hypervectors (D = 16,384)
+    "large16k": Workload("large16k", 1_000_000, 100_000, 16384),
     # precision (MFMA) form, same data as tiny
     "precision": Workload("precision", 2000, 200, 2048),
     # mixed narrow/open stream for the batched form

@@ -112,11 +112,13 @@ def test_top1(tiny, kind, value, engine):
 
 
 @pytest.mark.parametrize("dim,n_ref,n_query", [(8192, 1500, 333), (512, 700, 1000),
-                                              (1536, 3000, 257)])
+                                              (1536, 3000, 257), (16384, 1100, 301),
+                                              (32768, 500, 130)])
 def test_top1_other_dims_ragged(dim, n_ref, n_query):
-    """D = 8192 (Section 4.2) and other supported D, with query counts that
-    leave ragged tiles and library sizes that leave ragged row blocks; every
-    engine must agree with the oracle."""
+    """D = 8192 (Section 4.2) and other supported D, up to the higher-capacity
+    vectors of Section 4.3 (16,384) and the largest D the ABI accepts, with query
+    counts that leave ragged tiles and library sizes that leave ragged row
+    blocks; every engine must agree with the oracle."""
     s = Setup(dim=dim, n_ref=n_ref, n_query=n_query, seed=3)
     g = s.g
     try:
