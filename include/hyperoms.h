@@ -221,6 +221,35 @@ homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv
                                int32_t *d_out_dist, void *stream);
 
 /*
+ * Cascade search, Section 3.4, with target-decoy FDR filtering (Section 2.1;
+ * the fixed 1% level of Section 4.1 is fdr_level = 0.01). Stage 1 searches
+ * every query with the narrow window; stage 2 searches, with the wide
+ * window, every query that stage 1 did not identify. In each stage a PSM is a
+ * query's top-1 match (score D - distance) and is a decoy match when
+ * d_lib_decoy[its library index] != 0; FDR at distance threshold d = decoy
+ * PSMs / target PSMs at distance <= d over that stage's PSMs (undefined,
+ * never accepted, without a target); a PSM's q-value is the minimum FDR over
+ * thresholds at or above its distance; a target PSM with q-value <=
+ * fdr_level is an identification. Counts are exact and each FDR one IEEE
+ * double division, so results are deterministic.
+ * In:  queries as for homs_search_window; narrow and wide windows; engine =
+ *      HOMS_ENGINE_*; d_lib_decoy[library size] (device, library order, the
+ *      caller's indices); fdr_level in [0, 1].
+ * Out: d_out_stage[nq] (int8): 1 = identified in stage 1, 2 = in stage 2,
+ *      0 = not identified; d_out_idx / d_out_dist / d_out_qvalue[nq] (int64,
+ *      int32, double): the stage-1 match and q-value for stage-1
+ *      identifications, the stage-2 ones for every other query (-1, -1, +inf
+ *      when its wide window is empty).
+ * Asynchronous on `stream`; the workspace grows on first use of a larger nq.
+ */
+homs_status homs_cascade_search(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                                const double *d_q_pmz, const int8_t *d_q_charge,
+                                const homs_window *narrow, const homs_window *wide,
+                                int32_t engine, const uint8_t *d_lib_decoy, double fdr_level,
+                                int64_t *d_out_idx, int32_t *d_out_dist, int8_t *d_out_stage,
+                                double *d_out_qvalue, void *stream);
+
+/*
  * Tunables of homs_search_batched, chosen by homs_autotune_batched or set by
  * the caller.
  *  narrow_max    a query with at most this many candidates is scored on its

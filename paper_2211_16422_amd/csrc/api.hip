@@ -529,28 +529,30 @@ homs_status homs_window_bounds(homs_ctx* c, int64_t nq, const double* d_q_pmz,
     return HOMS_OK;
 }
 
-homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
-                               const double* d_q_pmz, const int8_t* d_q_charge,
-                               const homs_window* win, int32_t engine, int64_t* d_out_idx,
-                               int32_t* d_out_dist, void* stream)
+}  // extern "C"
+
+namespace {
+
+bool engine_valid(int32_t engine)
 {
-    if (homs_status s = usable(c)) return s;
-    std::string why;
-    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
-    if (engine != HOMS_ENGINE_POPCOUNT && engine != HOMS_ENGINE_MFMA_I8 &&
-        engine != HOMS_ENGINE_MFMA_F8 && engine != HOMS_ENGINE_MFMA_F4)
-        return fail(c, HOMS_E_INVALID, "unknown engine");
-    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
-    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
-    if (nq == 0) return HOMS_OK;
-    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist)
-        return fail(c, HOMS_E_INVALID, "NULL device pointer");
-    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
-    DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
-    const int tile = engine == HOMS_ENGINE_POPCOUNT ? homs::search_popcount_tile()
-                                                    : homs::search_mfma_tile();
-    if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, tile), s)) return st;
+    return engine == HOMS_ENGINE_POPCOUNT || engine == HOMS_ENGINE_MFMA_I8 ||
+           engine == HOMS_ENGINE_MFMA_F8 || engine == HOMS_ENGINE_MFMA_F4;
+}
+
+int engine_tile(int32_t engine)
+{
+    return engine == HOMS_ENGINE_POPCOUNT ? homs::search_popcount_tile()
+                                          : homs::search_mfma_tile();
+}
+
+// The search of homs_search_window on validated arguments. The workspace must
+// already hold search_scratch_bytes(nq, engine_tile(engine)) bytes; callers
+// may keep their own buffers after that region.
+homs_status run_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv, const double* d_q_pmz,
+                       const int8_t* d_q_charge, const homs_window* win, int32_t engine,
+                       int64_t* d_out_idx, int32_t* d_out_dist, hipStream_t s)
+{
+    const int tile = engine_tile(engine);
     SearchScratch w = carve(c->ws.ptr, nq, tile);
 
     hipEvent_t e0 = prof_mark(c, s);
@@ -583,6 +585,87 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     hipEvent_t e3 = prof_mark(c, s);
     prof_span(c, e0, e1, homs::kProfPrep);
     prof_span(c, e1, e2, homs::kProfSearch);
+    prof_span(c, e2, e3, homs::kProfPrep);
+    return HOMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                               const double* d_q_pmz, const int8_t* d_q_charge,
+                               const homs_window* win, int32_t engine, int64_t* d_out_idx,
+                               int32_t* d_out_dist, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!engine_valid(engine)) return fail(c, HOMS_E_INVALID, "unknown engine");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, engine_tile(engine)), s))
+        return st;
+    return run_search(c, nq, d_q_hv, d_q_pmz, d_q_charge, win, engine, d_out_idx, d_out_dist, s);
+}
+
+homs_status homs_cascade_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                                const double* d_q_pmz, const int8_t* d_q_charge,
+                                const homs_window* narrow, const homs_window* wide,
+                                int32_t engine, const uint8_t* d_lib_decoy, double fdr_level,
+                                int64_t* d_out_idx, int32_t* d_out_dist, int8_t* d_out_stage,
+                                double* d_out_qvalue, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(narrow, &why)) return fail(c, HOMS_E_INVALID, "narrow: " + why);
+    if (!window_valid(wide, &why)) return fail(c, HOMS_E_INVALID, "wide: " + why);
+    if (!engine_valid(engine)) return fail(c, HOMS_E_INVALID, "unknown engine");
+    if (!std::isfinite(fdr_level) || fdr_level < 0.0 || fdr_level > 1.0)
+        return fail(c, HOMS_E_INVALID, "fdr_level must be in [0, 1]");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "nq out of range");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_lib_decoy || !d_out_idx || !d_out_dist ||
+        !d_out_stage || !d_out_qvalue)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t dim = c->words * 32;
+    const size_t search_bytes = search_scratch_bytes(nq, engine_tile(engine));
+    const size_t off = (search_bytes + 255) & ~(size_t)255;
+    if (homs_status st = ensure_workspace(c, off + homs::cascade_scratch_bytes(nq, dim), s))
+        return st;
+    const homs::CascadeScratch w = homs::cascade_carve((char*)c->ws.ptr + off, nq, dim);
+
+    // stage 1: standard search with the narrow window, FDR over all its PSMs
+    if (homs_status st = run_search(c, nq, d_q_hv, d_q_pmz, d_q_charge, narrow, engine,
+                                    d_out_idx, d_out_dist, s))
+        return st;
+    hipEvent_t e0 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_fdr_stage(0, nq, dim, d_out_idx, d_out_dist, d_lib_decoy, fdr_level,
+                                      w, d_out_stage, d_out_qvalue, nullptr, nullptr, s),
+            "FDR kernels (narrow stage)");
+    HIP_TRY(c, homs::launch_mask_identified(nq, d_q_pmz, d_out_stage, w.pmz2, s),
+            "mask kernel");
+    hipEvent_t e1 = prof_mark(c, s);
+    prof_span(c, e0, e1, homs::kProfPrep);
+    // stage 2: open search of the queries not identified, FDR over their PSMs
+    if (homs_status st = run_search(c, nq, d_q_hv, w.pmz2, d_q_charge, wide, engine, w.idx2,
+                                    w.dist2, s))
+        return st;
+    hipEvent_t e2 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_fdr_stage(1, nq, dim, w.idx2, w.dist2, d_lib_decoy, fdr_level, w,
+                                      d_out_stage, d_out_qvalue, d_out_idx, d_out_dist, s),
+            "FDR kernels (open stage)");
+    hipEvent_t e3 = prof_mark(c, s);
     prof_span(c, e2, e3, homs::kProfPrep);
     return HOMS_OK;
 }

@@ -150,4 +150,24 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
 hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
                                     int32_t* qoff, hipStream_t s);
 
+// cascade.hip: FDR filtering between the stages of homs_cascade_search
+struct CascadeScratch {
+    double* pmz2;     // [nq] open-stage precursors (+inf for identified queries)
+    int64_t* idx2;    // [nq] open-stage top-1
+    int32_t* dist2;   // [nq]
+    uint32_t* hist;   // [2 (D + 1)] PSMs by distance: targets, then decoys
+    double* qtab;     // [D + 1] q-value of each distance
+};
+size_t cascade_scratch_bytes(int64_t nq, uint32_t dim);
+CascadeScratch cascade_carve(void* base, int64_t nq, uint32_t dim);
+// second = 0: PSMs of every query (idx, dist: narrow stage), sets stage and
+// qvalue; second = 1: PSMs of the queries with stage != 1 (idx, dist: open
+// stage), which also take these results into out_idx / out_dist
+hipError_t launch_fdr_stage(int second, int64_t nq, uint32_t dim, const int64_t* idx,
+                            const int32_t* dist, const uint8_t* lib_decoy, double level,
+                            const CascadeScratch& w, int8_t* stage, double* qvalue,
+                            int64_t* out_idx, int32_t* out_dist, hipStream_t s);
+hipError_t launch_mask_identified(int64_t nq, const double* pmz, const int8_t* stage,
+                                  double* pmz2, hipStream_t s);
+
 }  // namespace homs

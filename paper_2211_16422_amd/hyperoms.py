@@ -90,6 +90,9 @@ _sig("homs_library_size", [_P, ctypes.POINTER(_i64)])
 _sig("homs_library_export", [_P, _P, _P])
 _sig("homs_window_bounds", [_P, _i64, _P, _P, ctypes.POINTER(_Window), _P, _P, _P])
 _sig("homs_search_window", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P])
+_sig("homs_cascade_search", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window),
+                             ctypes.POINTER(_Window), _i32, _P, ctypes.c_double, _P, _P, _P, _P,
+                             _P])
 _sig("homs_debug_distances", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _P, _P, _P, _P])
 _sig("homs_device_errors", [_P, ctypes.POINTER(ctypes.c_uint32), _P])
 
@@ -122,7 +125,8 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_preprocess", "homs_create", "homs_destroy", "homs_generate_codebook", "homs_set_codebook",
             "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
             "homs_library_size", "homs_library_export", "homs_window_bounds",
-            "homs_search_window", "homs_debug_distances", "homs_device_errors",
+            "homs_search_window", "homs_cascade_search", "homs_debug_distances",
+            "homs_device_errors",
             "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
             "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched",
             "homs_model_create", "homs_model_destroy", "homs_model_set_weights",
@@ -380,6 +384,31 @@ class Context:
             _dptr(out_idx, torch.int64, "out_idx", self.device),
             _dptr(out_dist, torch.int32, "out_dist", self.device), _stream(self.device)))
         return out_idx, out_dist
+
+    def cascade_search(self, q_hv, pmz, charge, lib_decoy, narrow=(TOL_PPM, 20.0),
+                       wide=(TOL_DA, 500.0), engine=ENGINE_MFMA_F4, fdr_level=0.01):
+        """homs_cascade_search -> (library index int64, distance int32, stage int8,
+        q-value float64); lib_decoy: uint8 per library index (1 = decoy)."""
+        import torch
+        nq = pmz.shape[0]
+        if q_hv.shape != (nq, self.words):
+            raise ValueError("q_hv must be [nq, D/32]")
+        out_idx = torch.empty(nq, dtype=torch.int64, device=self.device)
+        out_dist = torch.empty(nq, dtype=torch.int32, device=self.device)
+        out_stage = torch.empty(nq, dtype=torch.int8, device=self.device)
+        out_q = torch.empty(nq, dtype=torch.float64, device=self.device)
+        wn = self._win(*narrow)
+        ww = self._win(*wide)
+        self._ck(_lib.homs_cascade_search(
+            self._h, nq, _dptr(q_hv, torch.int32, "q_hv", self.device),
+            _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(wn), ctypes.byref(ww),
+            engine, _dptr(lib_decoy, torch.uint8, "lib_decoy", self.device), float(fdr_level),
+            _dptr(out_idx, torch.int64, "out_idx", self.device),
+            _dptr(out_dist, torch.int32, "out_dist", self.device),
+            _dptr(out_stage, torch.int8, "out_stage", self.device),
+            _dptr(out_q, torch.float64, "out_q", self.device), _stream(self.device)))
+        return out_idx, out_dist, out_stage, out_q
 
     def debug_distances(self, q_hv, pmz, charge, kind=TOL_DA, value=500.0):
         """All candidates with distances: (row_off, lib index, dist) in sorted order."""
