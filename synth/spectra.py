@@ -87,13 +87,14 @@ def make_references(n: int, rng: np.random.Generator, charges=(2, 3),
                       shifted=np.zeros(n, dtype=bool))
 
 
-def make_decoys(refs: RawSpectra, rng: np.random.Generator) -> RawSpectra:
-    """One decoy per reference: its fragment m/z values permuted among its peaks."""
+def make_decoys(refs: RawSpectra, rng: np.random.Generator,
+                mz_range=(101.0, 1500.0)) -> RawSpectra:
+    """One decoy per reference, a spectrum that matches no peptide: the
+    reference's precursor m/z, charge, peak count and intensities, with every
+    fragment peak at a newly drawn m/z (the distribution of reference peaks)."""
     n = refs.n
-    npk = np.diff(refs.offsets)
-    seg = np.repeat(np.arange(n, dtype=np.float64), npk)
-    order = np.argsort(seg + rng.random(seg.shape[0]), kind="stable")
-    return RawSpectra(refs.offsets.copy(), refs.mz[order], refs.intensity.copy(),
+    mz = rng.uniform(mz_range[0], mz_range[1], size=refs.mz.shape[0])
+    return RawSpectra(refs.offsets.copy(), mz, refs.intensity.copy(),
                       refs.pmz.copy(), refs.charge.copy(),
                       source=np.arange(n, dtype=np.int64),
                       is_decoy=np.ones(n, dtype=bool),
@@ -191,6 +192,8 @@ WORKLOADS = {
     "large": Workload("large", 1_000_000, 100_000, 8192),
     # the same data in higher-capacity hypervectors (D = 16,384)
     "large16k": Workload("large16k", 1_000_000, 100_000, 16384),
+    # the same data searched as a cascade (narrow standard search, FDR, open search)
+    "cascade": Workload("cascade", 1_000_000, 100_000, 8192),
     # precision (MFMA) form, same data as tiny
     "precision": Workload("precision", 2000, 200, 2048),
     # mixed narrow/open stream for the batched form

@@ -341,8 +341,8 @@ def test_sampled_threshold_windows():
 
 def test_training_raises_agreement():
     """Trained on (query, exact top-1) pairs of separate training queries,
-    the model's k = 8 shortlist finds the exact top-1 of held-out queries more
-    often than the untrained model does."""
+    the model's k = 8 shortlist misses the exact top-1 of held-out queries at
+    least a fifth less often than the untrained model does."""
     import torch
     h = _h()
     s = LearnedSetup(n_query=400, seed=6, n_train=4096)
@@ -380,6 +380,6 @@ def test_training_raises_agreement():
         torch.cuda.synchronize()
         after = agreement()
         print(f"top-1 agreement at k={k}: untrained {before:.3f}, trained {after:.3f}")
-        assert after > before + 0.05, (before, after)
+        assert 1.0 - after < 0.8 * (1.0 - before), (before, after)
     finally:
         s.close()
