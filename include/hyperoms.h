@@ -134,6 +134,25 @@ homs_status homs_preprocess(const homs_params *p, int64_t n, const int64_t *h_of
                             uint8_t *h_out_level, int64_t *out_total, int32_t n_threads);
 
 /*
+ * The same preprocessing (Section 3.2; Table 1) on the context's device, with
+ * the context's parameters and identical results (float64 throughout), so
+ * that encoding can start from raw peaks already in device memory.
+ * In:  n spectra; d_offsets[n + 1] (int64 CSR, non-decreasing, d_offsets[0]
+ *      = 0); d_mz and d_intensity[d_offsets[n]] (float64, finite; intensity
+ *      >= 0). A spectrum may hold at most 2048 raw peaks: a larger one gets
+ *      no entries and raises device error bit 1 (homs_device_errors).
+ * Out: d_out_offsets[n + 1]; d_out_bin (int32) and d_out_level (uint8) with
+ *      room for min(d_offsets[n], n * top_n) entries: per spectrum its unique
+ *      bins in ascending order. All device pointers.
+ * Asynchronous on `stream`; uses the context's workspace (grows on first use
+ * of a larger n).
+ */
+homs_status homs_preprocess_device(homs_ctx *ctx, int64_t n, const int64_t *d_offsets,
+                                   const double *d_mz, const double *d_intensity,
+                                   int64_t *d_out_offsets, int32_t *d_out_bin,
+                                   uint8_t *d_out_level, void *stream);
+
+/*
  * Creates a context on HIP device `device` and generates the position and
  * level hypervectors from p->seed (Sections 3.3.1, 3.3.2): F_0 and the level
  * base L_0 are random bits, F_i flips the first floor(alpha*i/(f-1))
@@ -319,7 +338,8 @@ homs_status homs_debug_distances(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_
                                  int64_t *d_out_idx, int32_t *d_out_dist, void *stream);
 
 /* Reads and clears the context's device error flags (bit 0: a bin or level
- * out of range in an encode). Synchronous (waits for `stream`). */
+ * out of range in an encode; bit 1: a spectrum over the device preprocessing
+ * limit). Synchronous (waits for `stream`). */
 homs_status homs_device_errors(homs_ctx *ctx, uint32_t *flags, void *stream);
 
 /*

@@ -615,6 +615,28 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     return run_search(c, nq, d_q_hv, d_q_pmz, d_q_charge, win, engine, d_out_idx, d_out_dist, s);
 }
 
+homs_status homs_preprocess_device(homs_ctx* c, int64_t n, const int64_t* d_offsets,
+                                   const double* d_mz, const double* d_intensity,
+                                   int64_t* d_out_offsets, int32_t* d_out_bin,
+                                   uint8_t* d_out_level, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "n out of range");
+    if (!d_offsets || !d_out_offsets) return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (n > 0 && (!d_mz || !d_intensity || !d_out_bin || !d_out_level))
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (homs_status st = ensure_workspace(c, homs::prep_device_scratch_bytes(n), s)) return st;
+    hipEvent_t e0 = prof_mark(c, s);
+    HIP_TRY(c, homs::launch_preprocess_device(c, n, d_offsets, d_mz, d_intensity, d_out_offsets,
+                                              d_out_bin, d_out_level, c->ws.ptr, s),
+            "preprocess kernels");
+    hipEvent_t e1 = prof_mark(c, s);
+    prof_span(c, e0, e1, homs::kProfEncode);
+    return HOMS_OK;
+}
+
 homs_status homs_cascade_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
                                 const double* d_q_pmz, const int8_t* d_q_charge,
                                 const homs_window* narrow, const homs_window* wide,

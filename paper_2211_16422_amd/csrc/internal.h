@@ -14,6 +14,7 @@ namespace homs {
 
 // Device-side error flag bits.
 constexpr uint32_t kErrRange = 1u;  // bin >= f or level >= Q in an encode
+constexpr uint32_t kErrPeaks = 2u;  // a spectrum too large for device preprocessing
 
 struct Library {
     int64_t n = 0;
@@ -149,6 +150,14 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
                               uint64_t* keys, hipStream_t s);
 hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
                                     int32_t* qoff, hipStream_t s);
+
+// prep_device.hip: preprocessing of raw spectra on the device
+int prep_device_max_peaks();
+size_t prep_device_scratch_bytes(int64_t n);
+hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t* off,
+                                    const double* mz, const double* inten, int64_t* out_off,
+                                    int32_t* out_bin, uint8_t* out_level, void* scratch,
+                                    hipStream_t s);
 
 // cascade.hip: FDR filtering between the stages of homs_cascade_search
 struct CascadeScratch {

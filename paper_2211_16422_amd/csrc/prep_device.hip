@@ -1,0 +1,399 @@
+// Preprocessing on the device (Section 3.2, Table 1): raw peaks -> spectrum
+// vectors, the same steps and float64 arithmetic as the host path
+// (homs_preprocess), so encoding can start from raw m/z and intensities
+// already in HBM.
+//
+// Spectra of up to kWaveCap raw peaks (the usual case): one wave per
+// spectrum, no barriers. In-range peaks are compacted into the wave's LDS
+// (ballot positions), the noise floor is a wave maximum, a kept peak's place
+// in the top-N is its rank under (intensity desc, m/z asc, input position
+// asc) counted by the lane that owns it, the N kept peaks are placed in
+// (m/z asc, position asc) order by a second rank, and colliding bins are
+// summed by the lane holding their first peak, sequentially in m/z order (the
+// order that fixes the sums' rounding); normalisation and quantisation are
+// per bin. Larger spectra, up to kPrepCap raw peaks, go to a workgroup
+// kernel with bitonic sorts in LDS and one thread for the in-order sums; a
+// spectrum beyond that raises kErrPeaks and yields no entries. Every double
+// operation is an IEEE operation (no contraction; the device double square
+// root is correctly rounded), so results equal the host path's.
+//
+// Two passes over the spectra: the first counts each spectrum's unique bins,
+// an exclusive scan gives the CSR offsets, the second recomputes and writes.
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace homs {
+namespace {
+
+constexpr int kPrepThreads = 128;
+constexpr int kPrepCap = 2048;
+constexpr int kWaveCap = 256;
+constexpr int kWaves = 4;  // spectra per workgroup of the wave kernel
+
+struct PrepArgs {
+    double mz_min, mz_max, bins_per_da, noise_frac;
+    int64_t nbins;
+    uint32_t top_n, Q;
+};
+
+// bitonic sort of s[0, P) (P a power of two) under `before`, by the workgroup
+template <typename Before>
+__device__ void bitonic(double* a_mz, double* a_in, uint32_t* a_pos, int P, Before before)
+{
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const bool swap = up ? before(l, i) : before(i, l);
+                    if (swap) {
+                        const double tm = a_mz[i], ti = a_in[i];
+                        const uint32_t tp = a_pos[i];
+                        a_mz[i] = a_mz[l];
+                        a_in[i] = a_in[l];
+                        a_pos[i] = a_pos[l];
+                        a_mz[l] = tm;
+                        a_in[l] = ti;
+                        a_pos[l] = tp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
+    int write, int64_t n, const int64_t* __restrict__ off, const double* __restrict__ mz,
+    const double* __restrict__ inten, PrepArgs pa, int64_t* __restrict__ counts,
+    const int64_t* __restrict__ out_off, int32_t* __restrict__ out_bin,
+    uint8_t* __restrict__ out_level, uint32_t* __restrict__ err)
+{
+    __shared__ double s_mz[kPrepCap], s_in[kPrepCap];
+    __shared__ uint32_t s_pos[kPrepCap];
+    __shared__ double s_red[kPrepThreads];
+    __shared__ int s_m, s_k;
+    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
+        const int64_t p0 = off[s];
+        const int64_t np = off[s + 1] - p0;
+        if (np <= kWaveCap) continue;  // the wave kernel's
+        if (np > kPrepCap) {  // uniform
+            if (threadIdx.x == 0) {
+                atomicOr(err, kErrPeaks);
+                if (!write) counts[s] = 0;
+            }
+            continue;
+        }
+        if (threadIdx.x == 0) s_m = 0;
+        __syncthreads();
+        // 1. m/z range; 2. the maximum intensity of the peaks in range
+        double imax = 0.0;
+        for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
+            const double m = mz[p0 + p];
+            if (m >= pa.mz_min && m < pa.mz_max) {
+                const double v = inten[p0 + p];
+                const int slot = atomicAdd(&s_m, 1);
+                s_mz[slot] = m;
+                s_in[slot] = v;
+                s_pos[slot] = (uint32_t)p;
+                imax = v > imax ? v : imax;
+            }
+        }
+        s_red[threadIdx.x] = imax;
+        __syncthreads();
+        for (int o = kPrepThreads / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o)
+                s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + o]);
+            __syncthreads();
+        }
+        const int m = s_m;
+        const double floor_i = pa.noise_frac * s_red[0];
+        // peaks below the noise floor sort after the kept ones (kept >= 0),
+        // padding after everything
+        int P = 1;
+        while (P < m) P <<= 1;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            if (i >= m) {
+                s_in[i] = -INFINITY;
+                s_mz[i] = INFINITY;
+                s_pos[i] = 0xFFFFFFFFu;
+            } else if (s_in[i] < floor_i) {
+                s_in[i] = -1.0;
+            }
+        }
+        __syncthreads();
+        // 3. top-N: intensity desc, m/z asc, input position asc
+        bitonic(s_mz, s_in, s_pos, P, [&](int x, int y) {
+            if (s_in[x] != s_in[y]) return s_in[x] > s_in[y];
+            if (s_mz[x] != s_mz[y]) return s_mz[x] < s_mz[y];
+            return s_pos[x] < s_pos[y];
+        });
+        if (threadIdx.x == 0) {
+            int k = 0;
+            while (k < m && s_in[k] >= 0.0) ++k;  // kept peaks come first
+            s_k = k < (int)pa.top_n ? k : (int)pa.top_n;
+        }
+        __syncthreads();
+        const int k = s_k;
+        // 4. square roots of the kept intensities; the rest become padding
+        int P2 = 1;
+        while (P2 < k) P2 <<= 1;
+        for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+            if (i < k) {
+                s_in[i] = sqrt(s_in[i]);
+            } else {
+                s_mz[i] = INFINITY;
+                s_pos[i] = 0xFFFFFFFFu;
+            }
+        }
+        __syncthreads();
+        // 5. ascending m/z, then input position
+        bitonic(s_mz, s_in, s_pos, P2, [&](int x, int y) {
+            if (s_mz[x] != s_mz[y]) return s_mz[x] < s_mz[y];
+            return s_pos[x] < s_pos[y];
+        });
+        // 5-6. bins, sums of colliding peaks in ascending m/z, normalisation,
+        // levels: one thread, in order (the sums' rounding depends on it)
+        if (threadIdx.x == 0) {
+            int u = 0;
+            int32_t last = -1;
+            for (int i = 0; i < k; ++i) {
+                int64_t bn = (int64_t)floor((s_mz[i] - pa.mz_min) * pa.bins_per_da);
+                if (bn > pa.nbins - 1) bn = pa.nbins - 1;
+                if (bn < 0) bn = 0;
+                if (u > 0 && last == (int32_t)bn) {
+                    s_in[u - 1] = s_in[u - 1] + s_in[i];
+                } else {
+                    s_in[u] = s_in[i];  // u <= i: in place
+                    s_pos[u] = (uint32_t)bn;
+                    last = (int32_t)bn;
+                    ++u;
+                }
+            }
+            if (!write) {
+                counts[s] = u;
+            } else {
+                double smax = 0.0;
+                for (int i = 0; i < u; ++i) smax = s_in[i] > smax ? s_in[i] : smax;
+                const int64_t w0 = out_off[s];
+                for (int i = 0; i < u; ++i) {
+                    int64_t lv = 0;
+                    if (smax > 0.0) {
+                        const double v = s_in[i] / smax;
+                        lv = (int64_t)floor(v * (double)pa.Q);
+                        if (lv > (int64_t)pa.Q - 1) lv = (int64_t)pa.Q - 1;
+                    }
+                    out_bin[w0 + i] = (int32_t)s_pos[i];
+                    out_level[w0 + i] = (uint8_t)lv;
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next spectrum
+    }
+}
+
+// total order of the top-N selection: does peak x come before peak y?
+__device__ __forceinline__ bool before_int(double ix, double mx, uint32_t px, double iy, double my,
+                                           uint32_t py)
+{
+    if (ix != iy) return ix > iy;
+    if (mx != my) return mx < my;
+    return px < py;
+}
+
+__global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
+    int write, int64_t n, const int64_t* __restrict__ off, const double* __restrict__ mz,
+    const double* __restrict__ inten, PrepArgs pa, int64_t* __restrict__ counts,
+    const int64_t* __restrict__ out_off, int32_t* __restrict__ out_bin,
+    uint8_t* __restrict__ out_level)
+{
+    __shared__ double s_mz[kWaves][kWaveCap], s_in[kWaves][kWaveCap];
+    __shared__ uint16_t s_pos[kWaves][kWaveCap], s_top[kWaves][kWaveCap],
+        s_ord[kWaves][kWaveCap];
+    __shared__ int32_t s_bin[kWaves][kWaveCap];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double* const smz = s_mz[w];
+    double* const sin_ = s_in[w];
+    uint16_t* const spos = s_pos[w];
+    uint16_t* const stop = s_top[w];
+    uint16_t* const sord = s_ord[w];
+    int32_t* const sbin = s_bin[w];
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    for (int64_t s = (int64_t)blockIdx.x * kWaves + w; s < n; s += stride) {
+        const int64_t p0 = off[s];
+        const int np = (int)(off[s + 1] - p0);
+        if (np > kWaveCap) continue;  // the workgroup kernel's (uniform per wave)
+        // 1. in-range peaks into LDS, in input order; their maximum intensity
+        int m = 0;
+        double imax = 0.0;
+        for (int c = 0; c < np; c += 64) {
+            const int p = c + l;
+            double pm = 0.0, pi = 0.0;
+            bool ok = false;
+            if (p < np) {
+                pm = mz[p0 + p];
+                pi = inten[p0 + p];
+                ok = pm >= pa.mz_min && pm < pa.mz_max;
+            }
+            const uint64_t b = __ballot(ok);
+            if (ok) {
+                const int slot = m + (int)__builtin_amdgcn_mbcnt_hi(
+                                         (uint32_t)(b >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                smz[slot] = pm;
+                sin_[slot] = pi;
+                spos[slot] = (uint16_t)p;
+                imax = pi > imax ? pi : imax;
+            }
+            m += __popcll(b);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v = __shfl_xor(imax, o);
+            imax = v > imax ? v : imax;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 2. noise floor; 3. rank of each kept peak in the top-N order
+        const double floor_i = pa.noise_frac * imax;
+        int kept = 0;
+        for (int e = l; e < m; e += 64) kept += !(sin_[e] < floor_i);
+        for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o);
+        const int k = kept < (int)pa.top_n ? kept : (int)pa.top_n;
+        for (int e = l; e < m; e += 64) {
+            const double ie = sin_[e], me = smz[e];
+            const uint32_t pe = spos[e];
+            if (ie < floor_i) continue;
+            int r = 0;
+            for (int j = 0; j < m; ++j) {
+                const double ij = sin_[j];
+                r += (!(ij < floor_i) && before_int(ij, smz[j], spos[j], ie, me, pe)) ? 1 : 0;
+            }
+            if (r < k) stop[r] = (uint16_t)e;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 4-5. the top-N in (m/z asc, position asc) order
+        for (int t = l; t < k; t += 64) {
+            const int e = stop[t];
+            const double me = smz[e];
+            const uint32_t pe = spos[e];
+            int r = 0;
+            for (int u = 0; u < k; ++u) {
+                const int f = stop[u];
+                const double mf = smz[f];
+                r += (mf < me || (mf == me && spos[f] < pe)) ? 1 : 0;
+            }
+            sord[r] = (uint16_t)e;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int t = l; t < k; t += 64) {
+            int64_t bn = (int64_t)floor((smz[sord[t]] - pa.mz_min) * pa.bins_per_da);
+            if (bn > pa.nbins - 1) bn = pa.nbins - 1;
+            if (bn < 0) bn = 0;
+            sbin[t] = (int32_t)bn;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 5-6. bins: the lane of a bin's first peak sums its peaks' square
+        // roots in m/z order; then the largest sum, levels and output
+        int u_total = 0;
+        double smax = 0.0;
+        for (int c = 0; c < k; c += 64) {
+            const int t = c + l;
+            const bool first = t < k && (t == 0 || sbin[t] != sbin[t - 1]);
+            if (first) {
+                double sum = sqrt(sin_[sord[t]]);
+                for (int v = t + 1; v < k && sbin[v] == sbin[t]; ++v) sum = sum + sqrt(sin_[sord[v]]);
+                smax = sum > smax ? sum : smax;
+            }
+            u_total += __popcll(__ballot(first));
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v = __shfl_xor(smax, o);
+            smax = v > smax ? v : smax;
+        }
+        if (!write) {
+            if (l == 0) counts[s] = u_total;
+            continue;
+        }
+        int64_t w0 = out_off[s];
+        for (int c = 0; c < k; c += 64) {
+            const int t = c + l;
+            const bool first = t < k && (t == 0 || sbin[t] != sbin[t - 1]);
+            const uint64_t b = __ballot(first);
+            if (first) {
+                double sum = sqrt(sin_[sord[t]]);
+                for (int v = t + 1; v < k && sbin[v] == sbin[t]; ++v) sum = sum + sqrt(sin_[sord[v]]);
+                int64_t lv = 0;
+                if (smax > 0.0) {
+                    const double val = sum / smax;
+                    lv = (int64_t)floor(val * (double)pa.Q);
+                    if (lv > (int64_t)pa.Q - 1) lv = (int64_t)pa.Q - 1;
+                }
+                const int64_t at = w0 + (int64_t)__builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(b >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                out_bin[at] = sbin[t];
+                out_level[at] = (uint8_t)lv;
+            }
+            w0 += __popcll(b);
+        }
+        __builtin_amdgcn_wave_barrier();  // LDS is reused by the wave's next spectrum
+    }
+}
+
+__global__ void offsets_tail_kernel(int64_t n, const int64_t* counts, int64_t* out_off)
+{
+    // out_off[0, n) holds the exclusive scan; the total closes the CSR
+    out_off[n] = n > 0 ? out_off[n - 1] + counts[n - 1] : 0;
+}
+
+}  // namespace
+
+int prep_device_max_peaks() { return kPrepCap; }
+
+size_t prep_device_scratch_bytes(int64_t n)
+{
+    size_t temp = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp, (const int64_t*)nullptr,
+                                          (int64_t*)nullptr, (int)n);
+    return ((size_t)n * 8 + 255) / 256 * 256 + temp;
+}
+
+hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t* off,
+                                    const double* mz, const double* inten, int64_t* out_off,
+                                    int32_t* out_bin, uint8_t* out_level, void* scratch,
+                                    hipStream_t s)
+{
+    if (n <= 0) {
+        return hipMemsetAsync(out_off, 0, sizeof(int64_t), s);
+    }
+    PrepArgs pa{c->p.mz_min, c->p.mz_max, c->p.bins_per_da, c->p.noise_frac, c->n_bins,
+                c->p.top_n, c->p.n_levels};
+    int64_t* counts = (int64_t*)scratch;
+    void* temp = (char*)scratch + ((size_t)n * 8 + 255) / 256 * 256;
+    size_t temp_bytes = 0;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, counts, out_off, (int)n,
+                                                    s);
+    if (e != hipSuccess) return e;
+    const uint32_t grid = (uint32_t)(n < 8192 ? n : 8192);
+    const int64_t wgrid64 = (n + kWaves - 1) / kWaves;
+    const uint32_t wgrid = (uint32_t)(wgrid64 < 65536 ? wgrid64 : 65536);
+    for (int write = 0; write < 2; ++write) {
+        preprocess_wave_kernel<<<wgrid, 64 * kWaves, 0, s>>>(write, n, off, mz, inten, pa, counts,
+                                                             out_off, out_bin, out_level);
+        preprocess_kernel<<<grid, kPrepThreads, 0, s>>>(write, n, off, mz, inten, pa, counts,
+                                                        out_off, out_bin, out_level, c->d_err);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (!write) {
+            e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, counts, out_off, (int)n, s);
+            if (e != hipSuccess) return e;
+            offsets_tail_kernel<<<1, 1, 0, s>>>(n, counts, out_off);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace homs

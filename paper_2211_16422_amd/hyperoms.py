@@ -90,6 +90,7 @@ _sig("homs_library_size", [_P, ctypes.POINTER(_i64)])
 _sig("homs_library_export", [_P, _P, _P])
 _sig("homs_window_bounds", [_P, _i64, _P, _P, ctypes.POINTER(_Window), _P, _P, _P])
 _sig("homs_search_window", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P])
+_sig("homs_preprocess_device", [_P, _i64, _P, _P, _P, _P, _P, _P, _P])
 _sig("homs_cascade_search", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window),
                              ctypes.POINTER(_Window), _i32, _P, ctypes.c_double, _P, _P, _P, _P,
                              _P])
@@ -125,7 +126,8 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_preprocess", "homs_create", "homs_destroy", "homs_generate_codebook", "homs_set_codebook",
             "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
             "homs_library_size", "homs_library_export", "homs_window_bounds",
-            "homs_search_window", "homs_cascade_search", "homs_debug_distances",
+            "homs_search_window", "homs_cascade_search", "homs_preprocess_device",
+            "homs_debug_distances",
             "homs_device_errors",
             "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
             "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched",
@@ -384,6 +386,26 @@ class Context:
             _dptr(out_idx, torch.int64, "out_idx", self.device),
             _dptr(out_dist, torch.int32, "out_dist", self.device), _stream(self.device)))
         return out_idx, out_dist
+
+    def preprocess_device(self, offsets, mz, intensity):
+        """homs_preprocess_device: raw peaks (device CSR: int64 offsets, float64 m/z and
+        intensities) -> device CSR (offsets int64, bins int32, levels uint8)."""
+        import torch
+        n = offsets.shape[0] - 1
+        raw = int(offsets[-1].item()) if n > 0 else 0
+        cap = max(1, min(raw, n * int(self.params.top_n)))
+        out_off = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        out_bin = torch.empty(cap, dtype=torch.int32, device=self.device)
+        out_lv = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        self._ck(_lib.homs_preprocess_device(
+            self._h, n, _dptr(offsets, torch.int64, "offsets", self.device),
+            _dptr(mz, torch.float64, "mz", self.device),
+            _dptr(intensity, torch.float64, "intensity", self.device),
+            _dptr(out_off, torch.int64, "out_offsets", self.device),
+            _dptr(out_bin, torch.int32, "out_bin", self.device),
+            _dptr(out_lv, torch.uint8, "out_level", self.device), _stream(self.device)))
+        total = int(out_off[-1].item())
+        return out_off, out_bin[:total], out_lv[:total]
 
     def cascade_search(self, q_hv, pmz, charge, lib_decoy, narrow=(TOL_PPM, 20.0),
                        wide=(TOL_DA, 500.0), engine=ENGINE_MFMA_F4, fdr_level=0.01):
