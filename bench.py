@@ -158,6 +158,7 @@ def main():
     log(f"library encoded and sorted on the GPU in {lib_encode_s:.3f}s")
     del l_dev
     prep = prep_device_measure(ctx, lib, l_csr, dev, host_prep_s)
+    encodings = encodings_measure(w, l_csr, l_pmz, l_ch, dev, lib_encode_s)
 
     lo, hi = ctx.window_bounds(q_pmz, q_ch, h.TOL_DA, 500.0)
     pairs = int((hi - lo).sum().item())
@@ -286,6 +287,7 @@ def main():
         "queries_per_s": qps,
         "library_encode_s": lib_encode_s,
         "prep_device": prep,
+        "library_encode_s_by_encoding": encodings,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
@@ -553,6 +555,29 @@ def bench_learned(args, w, dev):
     print(json.dumps(line), flush=True)
     model.close()
     ctx.close()
+
+
+def encodings_measure(w, l_csr, l_pmz, l_ch, dev, id_level_s):
+    """Library encode + sort time with the encoding baselines of Section 4.2
+    (random position vectors; random-projection LSH) beside the paper's."""
+    import torch
+
+    import paper_2211_16422_amd.hyperoms as h
+    out = {"id_level": round(id_level_s, 4)}
+    for name, enc in (("random_id", h.ENCODING_RANDOM_ID), ("lsh", h.ENCODING_LSH)):
+        c2 = h.Context(h.Params(dim=w.dim, n_levels=w.n_levels, bins_per_da=w.bins_per_da,
+                                encoding=enc), device=0)
+        l_dev = h.to_device_csr(*l_csr, dev)
+        c2.encode_library(*l_dev, l_pmz, l_ch)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2.encode_library(*l_dev, l_pmz, l_ch)
+        torch.cuda.synchronize()
+        out[name] = round(time.perf_counter() - t0, 4)
+        c2.close()
+        del l_dev
+    log(f"library encode + sort by encoding (s): {out}")
+    return out
 
 
 def prep_device_measure(ctx, lib, l_csr, dev, host_prep_s):

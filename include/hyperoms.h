@@ -61,6 +61,9 @@ typedef struct homs_ctx homs_ctx;
  *  charge_match 1: candidates must share the query's charge (Section 3.4);
  *               0: charge is ignored.
  *  seed         seed of the codebook's SplitMix64 stream.
+ *  encoding     HOMS_ENCODING_*: the paper's ID-level encoding (Section 3.3),
+ *               or one of the two baselines it is compared with in Section
+ *               4.2 (Fig. 4(c)).
  */
 typedef struct homs_params {
     uint32_t struct_size; /* sizeof(homs_params) */
@@ -74,7 +77,21 @@ typedef struct homs_params {
     uint32_t id_flips;
     uint32_t charge_match;
     uint64_t seed;
+    uint32_t encoding;
+    uint32_t reserved;
 } homs_params;
+
+/* Encodings. ID_LEVEL: Eq. 1 with position vectors that keep locality
+ * (Section 3.3.1) bound to level vectors (Section 3.3.2). RANDOM_ID: the same
+ * binding and majority with independent random position vectors (the
+ * ID-level HDC baseline of Section 4.2). LSH: random-projection hashing of
+ * the spectrum vector (Section 4.2): bit d = 0 if sum over kept bins of
+ * (level + 1) x (+1 or -1, bit d of the bin's random row) > 0, else 1. For
+ * RANDOM_ID and LSH, row i of the position table is the next D/64 outputs of
+ * the codebook stream after the level table's draws. */
+#define HOMS_ENCODING_ID_LEVEL 0
+#define HOMS_ENCODING_RANDOM_ID 1
+#define HOMS_ENCODING_LSH 2
 
 /* Precursor tolerance (Section 3.4; Table 1): kind 0 = +-value Da,
  * kind 1 = +-value ppm of the query precursor m/z, i.e. pmz * value / 1e6.

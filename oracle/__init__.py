@@ -50,7 +50,8 @@ def _load():
         i64, u32, u64, i32, f64 = (ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
                                    ctypes.c_int32, ctypes.c_double)
         _lib.oracle_splitmix64.argtypes = [u64, i64, P]
-        _lib.oracle_codebook.argtypes = [u32, u32, u32, u32, u64, P, P]
+        _lib.oracle_codebook.argtypes = [u32, u32, u32, u32, u64, u32, P, P]
+        _lib.oracle_encode_lsh.argtypes = [u32, P, i64, P, P, P, P]
         _lib.oracle_codebook.restype = ctypes.c_int
         _lib.oracle_num_bins.argtypes = [f64, f64, f64]
         _lib.oracle_num_bins.restype = i64
@@ -86,6 +87,10 @@ class Params:
     noise_frac: float = 0.01
     id_flips: int = 0  # alpha; 0 means D/2
     seed: int = 0
+    # 0: the paper's ID-level encoding with locality (Section 3.3); the
+    # baselines of Section 4.2: 1 random (independent) position vectors,
+    # 2 random-projection LSH
+    encoding: int = 0
 
     @property
     def alpha(self) -> int:
@@ -116,7 +121,7 @@ def codebook(p: Params) -> Tuple[np.ndarray, np.ndarray]:
     idt = np.zeros((f, p.words), dtype=np.uint32)
     lvt = np.zeros((p.n_levels, p.words), dtype=np.uint32)
     rc = _load().oracle_codebook(p.dim, f, p.n_levels, p.alpha, ctypes.c_uint64(p.seed),
-                                 _p(idt), _p(lvt))
+                                 p.encoding, _p(idt), _p(lvt))
     if rc != 0:
         raise ValueError("invalid codebook parameters")
     return idt, lvt
@@ -141,7 +146,8 @@ def preprocess(offsets, mz, intensity, p: Params):
 
 
 def encode(p: Params, idt, lvt, offsets, bins, levels) -> np.ndarray:
-    """Eq. 1 + binarisation for every spectrum: uint32 [n, D/32]."""
+    """Eq. 1 + binarisation for every spectrum (or, with p.encoding == 2, the
+    random-projection baseline): uint32 [n, D/32]."""
     off = _c(offsets, np.int64)
     b = _c(bins, np.int32)
     lv = _c(levels, np.uint8)
@@ -156,7 +162,10 @@ def encode(p: Params, idt, lvt, offsets, bins, levels) -> np.ndarray:
     if b.size == 0:
         b = np.zeros(1, dtype=np.int32)
         lv = np.zeros(1, dtype=np.uint8)
-    _load().oracle_encode(p.dim, _p(idt), _p(lvt), n, _p(off), _p(b), _p(lv), _p(out))
+    if p.encoding == 2:
+        _load().oracle_encode_lsh(p.dim, _p(idt), n, _p(off), _p(b), _p(lv), _p(out))
+    else:
+        _load().oracle_encode(p.dim, _p(idt), _p(lvt), n, _p(off), _p(b), _p(lv), _p(out))
     return out
 
 

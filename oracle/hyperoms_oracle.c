@@ -96,8 +96,13 @@ static void random_permutation(uint64_t *state, uint32_t D, uint32_t *perm)
  * id_out: f rows of D/32 words; lv_out: Q rows of D/32 words.
  * Returns 0, or -1 for D not a multiple of 64, f == 0, Q < 2, alpha > D.
  */
+/* encoding 0: position vectors with locality (Section 3.3.1); 1 and 2 (the
+ * random-ID and random-projection baselines of Section 4.2): every position
+ * vector is independent random bits, drawn row after row from the same
+ * stream after the level table. */
 ORACLE_API int oracle_codebook(uint32_t D, uint32_t f, uint32_t Q, uint32_t alpha,
-                               uint64_t seed, uint32_t *id_out, uint32_t *lv_out)
+                               uint64_t seed, uint32_t encoding, uint32_t *id_out,
+                               uint32_t *lv_out)
 {
     if (D == 0 || D % 64 != 0 || f == 0 || Q < 2 || alpha > D) return -1;
     const uint32_t W = D / 32;
@@ -123,6 +128,8 @@ ORACLE_API int oracle_codebook(uint32_t D, uint32_t f, uint32_t Q, uint32_t alph
         memcpy(row, base, (size_t)W * sizeof(uint32_t));
         for (uint64_t t = 0; t < m; ++t) flip_bit(row, perm[t]);
     }
+    if (encoding != 0)
+        for (uint32_t i = 0; i < f; ++i) random_bits(&state, D, id_out + (size_t)i * W);
     free(base);
     free(perm);
     return 0;
@@ -294,6 +301,35 @@ ORACLE_API void oracle_encode(uint32_t D, const uint32_t *id, const uint32_t *lv
                 if (!(I[d] > 0)) o[d >> 5] |= (1u << (d & 31));
         }
         free(I);
+    }
+}
+
+/* Random-projection LSH baseline (Section 4.2): the spectrum vector, with
+ * each kept bin weighted by (level + 1), projected on the random +-1 rows
+ * (bit 0 = +1): S_d = sum over peaks of w * (+1 or -1); bit d = 0 if S_d > 0,
+ * else 1 (the tie rule of Eq. 1's binarisation). */
+ORACLE_API void oracle_encode_lsh(uint32_t D, const uint32_t *id, int64_t n, const int64_t *off,
+                                  const int32_t *bin, const uint8_t *level, uint32_t *out)
+{
+    const uint32_t W = D / 32;
+#pragma omp parallel
+    {
+        int64_t *S = (int64_t *)malloc((size_t)D * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t s = 0; s < n; ++s) {
+            for (uint32_t d = 0; d < D; ++d) S[d] = 0;
+            for (int64_t p = off[s]; p < off[s + 1]; ++p) {
+                const uint32_t *R = id + (size_t)bin[p] * W;
+                const int64_t w = (int64_t)level[p] + 1;
+                for (uint32_t d = 0; d < D; ++d)
+                    S[d] += ((R[d >> 5] >> (d & 31)) & 1u) ? -w : w;
+            }
+            uint32_t *o = out + (size_t)s * W;
+            for (uint32_t wd = 0; wd < W; ++wd) o[wd] = 0;
+            for (uint32_t d = 0; d < D; ++d)
+                if (!(S[d] > 0)) o[d >> 5] |= (1u << (d & 31));
+        }
+        free(S);
     }
 }
 

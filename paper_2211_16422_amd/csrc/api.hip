@@ -77,6 +77,11 @@ bool params_valid(const homs_params* p, std::string* why)
         *why = "n_levels must be in [2, 255]";
         return false;
     }
+    if (p->encoding != HOMS_ENCODING_ID_LEVEL && p->encoding != HOMS_ENCODING_RANDOM_ID &&
+        p->encoding != HOMS_ENCODING_LSH) {
+        *why = "encoding must be HOMS_ENCODING_ID_LEVEL, _RANDOM_ID or _LSH";
+        return false;
+    }
     if (p->top_n < 1) {
         *why = "top_n must be >= 1";
         return false;
@@ -335,7 +340,7 @@ homs_status homs_create(const homs_params* p, int32_t device, homs_ctx** out)
         return fail(nullptr, HOMS_E_OOM, "host allocation failed (codebook)");
     }
     homs::generate_codebook(p->dim, (uint32_t)c->n_bins, p->n_levels, c->p.id_flips, p->seed,
-                            id.data(), lv.data());
+                            p->encoding, id.data(), lv.data());
     hipError_t e = hipMalloc(&c->d_id, id.size() * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_level, lv.size() * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_err, 256);
@@ -357,8 +362,8 @@ homs_status homs_generate_codebook(const homs_params* p, uint32_t* h_id, uint32_
     if (!params_valid(p, &why)) return fail(nullptr, HOMS_E_INVALID, why);
     if (!h_id || !h_level) return fail(nullptr, HOMS_E_INVALID, "NULL output table");
     const uint32_t alpha = p->id_flips == 0 ? p->dim / 2 : p->id_flips;
-    homs::generate_codebook(p->dim, (uint32_t)homs_num_bins(p), p->n_levels, alpha, p->seed, h_id,
-                            h_level);
+    homs::generate_codebook(p->dim, (uint32_t)homs_num_bins(p), p->n_levels, alpha, p->seed,
+                            p->encoding, h_id, h_level);
     return HOMS_OK;
 }
 

@@ -72,7 +72,7 @@ void fill_table(uint32_t D, uint32_t rows, uint64_t total_flips, const uint32_t*
 }  // namespace
 
 void generate_codebook(uint32_t D, uint32_t f, uint32_t Q, uint32_t alpha, uint64_t seed,
-                       uint32_t* id_table, uint32_t* level_table)
+                       uint32_t encoding, uint32_t* id_table, uint32_t* level_table)
 {
     SplitMix64 g{seed};
     std::vector<uint32_t> base(D / 32);
@@ -82,6 +82,10 @@ void generate_codebook(uint32_t D, uint32_t f, uint32_t Q, uint32_t alpha, uint6
     base_row(g, D, base.data());
     order = flip_order(g, D);
     fill_table(D, Q, D / 2, base.data(), order, level_table);
+    // the baselines of Section 4.2: independent random position vectors,
+    // drawn row after row after the level table's draws
+    if (encoding != 0)
+        for (uint32_t i = 0; i < f; ++i) base_row(g, D, id_table + (size_t)i * (D / 32));
 }
 
 }  // namespace homs

@@ -10,6 +10,12 @@
 // The bipolar sum is I = n - 2c (n peaks, c components equal to -1), so the
 // binarised bit (1 unless I > 0) is c >= ceil(n/2), evaluated on the planes
 // with a bit-sliced comparison against that constant.
+//
+// The random-projection baseline of Section 4.2 weights bin i's random row by
+// w = level + 1 instead of binding it with a level vector: S = W - 2c with
+// W = sum of the weights and c the weighted count of -1 components, added to
+// the planes as w's binary digits (the row's bits enter plane k for every
+// set bit k of w); the bit is c >= ceil(W/2) again.
 #include "internal.h"
 
 namespace homs {
@@ -95,6 +101,84 @@ __device__ __forceinline__ U4 encode_one(const uint4* __restrict__ id, const uin
     return at_least<P>(c, (n_ok + 1u) / 2u);
 }
 
+// add x * w to the counters: x enters plane k for every set bit k of w
+template <int P>
+__device__ __forceinline__ void add_weighted(U4 (&c)[P], const U4& x, uint32_t w)
+{
+#pragma unroll
+    for (int k0 = 0; k0 < 9; ++k0) {  // w <= 256
+        if (!((w >> k0) & 1u)) continue;  // uniform over the lane group
+        U4 y = x;
+#pragma unroll
+        for (int k = k0; k < P; ++k) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t carry = c[k].v[e] & y.v[e];
+                c[k].v[e] ^= y.v[e];
+                y.v[e] = carry;
+            }
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ U4 encode_one_lsh(const uint4* __restrict__ id, uint32_t w4,
+                                             uint32_t lane, int64_t a, int64_t b,
+                                             const int32_t* __restrict__ bin,
+                                             const uint8_t* __restrict__ level, int64_t n_bins,
+                                             uint32_t n_levels, uint32_t* __restrict__ err)
+{
+    U4 c[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[k].v[e] = 0u;
+    uint32_t W = 0;
+    for (int64_t p = a; p < b; ++p) {
+        const int32_t bi = bin[p];
+        const uint32_t lj = level[p];
+        if (bi < 0 || (int64_t)bi >= n_bins || lj >= n_levels) {
+            if (lane == 0) atomicOr(err, kErrRange);
+            continue;
+        }
+        const uint4 f = id[(size_t)bi * w4 + lane];
+        U4 x;
+        x.v[0] = f.x;
+        x.v[1] = f.y;
+        x.v[2] = f.z;
+        x.v[3] = f.w;
+        add_weighted<P>(c, x, lj + 1u);
+        W += lj + 1u;
+    }
+    return at_least<P>(c, (W + 1u) / 2u);
+}
+
+__global__ __launch_bounds__(256) void encode_lsh_kernel(
+    const uint4* __restrict__ id, uint32_t w4, uint32_t per_block, int64_t n,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ bin,
+    const uint8_t* __restrict__ level, int64_t n_bins, uint32_t n_levels,
+    const uint32_t* __restrict__ slot, uint4* __restrict__ out, uint32_t* __restrict__ err)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t sub = t / w4;
+    const uint32_t lane = t - sub * w4;
+    if (sub >= per_block) return;
+    const int64_t s = (int64_t)blockIdx.x * per_block + sub;
+    if (s >= n) return;
+    const int64_t a = off[s], b = off[s + 1];
+    const int64_t np = b - a;
+    // planes for the largest weighted count: np * 256
+    U4 r;
+    if (np < 64)
+        r = encode_one_lsh<14>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    else if (np < 256)
+        r = encode_one_lsh<16>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    else
+        r = encode_one_lsh<32>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    const int64_t row = slot ? (int64_t)slot[s] : s;
+    out[(size_t)row * w4 + lane] = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+}
+
 __global__ __launch_bounds__(256) void encode_kernel(
     const uint4* __restrict__ id, const uint4* __restrict__ lv, uint32_t w4, uint32_t per_block,
     int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ bin,
@@ -132,6 +216,12 @@ hipError_t launch_encode(const homs_ctx* c, int64_t n, const int64_t* off, const
     const uint32_t w4 = c->words / 4;  // lanes per spectrum
     const uint32_t per_block = 256u / w4;
     const int64_t blocks = (n + per_block - 1) / per_block;
+    if (c->p.encoding == HOMS_ENCODING_LSH) {
+        encode_lsh_kernel<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
+            reinterpret_cast<const uint4*>(c->d_id), w4, per_block, n, off, bin, level,
+            c->n_bins, c->p.n_levels, slot, reinterpret_cast<uint4*>(out), c->d_err);
+        return hipGetLastError();
+    }
     encode_kernel<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
         reinterpret_cast<const uint4*>(c->d_id), reinterpret_cast<const uint4*>(c->d_level), w4,
         per_block, n, off, bin, level, c->n_bins, c->p.n_levels, slot,

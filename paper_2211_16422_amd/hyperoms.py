@@ -40,6 +40,10 @@ ENGINE_MFMA_I8 = 1
 ENGINE_MFMA_F8 = 2
 ENGINE_MFMA_F4 = 3
 
+ENCODING_ID_LEVEL = 0
+ENCODING_RANDOM_ID = 1
+ENCODING_LSH = 2
+
 
 class HomsError(RuntimeError):
     def __init__(self, status: int, msg: str):
@@ -53,7 +57,8 @@ class _Params(ctypes.Structure):
                 ("mz_min", ctypes.c_double), ("mz_max", ctypes.c_double),
                 ("bins_per_da", ctypes.c_double), ("noise_frac", ctypes.c_double),
                 ("id_flips", ctypes.c_uint32), ("charge_match", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("encoding", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class _Window(ctypes.Structure):
@@ -172,6 +177,7 @@ class Params:
     id_flips: int = 0
     charge_match: bool = True
     seed: int = 0
+    encoding: int = 0  # ENCODING_*
 
     def _c(self) -> _Params:
         p = _Params()
@@ -180,6 +186,7 @@ class Params:
         p.mz_min, p.mz_max = self.mz_min, self.mz_max
         p.bins_per_da, p.noise_frac = self.bins_per_da, self.noise_frac
         p.id_flips, p.charge_match, p.seed = self.id_flips, int(self.charge_match), self.seed
+        p.encoding = self.encoding
         return p
 
     @property

@@ -41,6 +41,15 @@ def test_codebook_matches_oracle(h, dim, bpd):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("encoding", [1, 2])
+def test_baseline_codebooks_match_oracle(h, encoding):
+    """Random position rows of the Section 4.2 baselines, generated on the
+    host by the library and by the oracle from the same stream."""
+    a = h.generate_codebook(h.Params(dim=1024, seed=3, encoding=encoding))
+    b = oracle.codebook(oracle.Params(dim=1024, seed=3, encoding=encoding))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_preprocess_matches_oracle(h):
     g = make_workload(WORKLOADS["tiny"], n_ref=3000, n_query=500, seed=2)
     for raw in (g.library, g.queries):
