@@ -245,24 +245,27 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
 // cores and appends every in-window pair at or above the query's threshold.
 //
-// Eight waves, two per SIMD, so that one wave's epilogue runs while the other
-// wave's matrix instructions do: wave (wr, wn) owns rows 64 wr .. + 63 (two
-// 32-row tiles) of each block and the 32 queries of column wn, whose
-// embeddings are its B operands for the whole chunk (E / 16 registers of 16
-// bytes). Library rows stream through two LDS buffers filled by direct
-// global-to-LDS loads (global_load_lds_dwordx4, no staging registers) two
-// blocks ahead of their use, one padded row per half-wave load so that every
-// A read is a base plus an immediate and the 16 rows read together by a
-// quarter-wave hit distinct banks. The loads are issued from inline asm with
-// explicit vmcnt waits: the compiler would otherwise drain every outstanding
-// LDS load before any LDS read and cap the prefetch at one block.
+// Eight waves, two per SIMD: wave (wr, wn) owns rows 32 wr .. + 31 of each
+// block and the 64 queries of half wn (two 32-query tiles), whose embeddings
+// are its B operands for the whole chunk (2 E / 16 registers of 16 bytes), so
+// every A operand read from LDS feeds two matrix instructions. Library rows
+// stream through two LDS buffers filled by direct global-to-LDS loads
+// (global_load_lds_dwordx4, no staging registers) two blocks ahead of their
+// use, one padded row per half-wave load so that every A read is a base plus
+// an immediate and the 16 rows read together by a quarter-wave hit distinct
+// banks. The loads are issued from inline asm with explicit vmcnt waits: the
+// compiler would otherwise drain every outstanding LDS load before any LDS
+// read and cap the prefetch at one block.
 //
-// Epilogue: one compare per pair when the lane's 60 rows of the block lie
-// inside its window (the usual case); a position is skipped unless some lane
-// of the wave hits (a scalar branch on the ballot); hits go to the wave's own
-// LDS list at positions counted from the ballot (no atomics, no global
-// loads), which is flushed to the per-query global buffers when half full
-// and at the end.
+// Epilogue, software-pipelined: the scores of block b - 1 are examined
+// between the matrix instructions of block b (one position per step, both
+// query tiles), so that the compares and ballots issue while the matrix core
+// works. When every lane's 28 rows of the block lie inside its windows (the
+// usual case) a position costs one compare and one ballot per tile and is
+// skipped unless some lane hits; otherwise the block's positions are masked
+// row by row after the matrix instructions. Hits go to the wave's own LDS
+// list at positions counted from the ballot (no atomics, no global loads),
+// flushed to the per-query global buffers when half full and at the end.
 constexpr int kWaveList = 256;  // LDS entries per wave
 
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
@@ -274,16 +277,18 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
-    const uint16_t* __restrict__ lib_emb, const uint32_t* __restrict__ lib_orig,
-    uint32_t* __restrict__ count, uint64_t* __restrict__ buf)
+    const uint16_t* __restrict__ lib_emb, uint32_t* __restrict__ count,
+    uint64_t* __restrict__ buf)
 {
     using namespace gemm;
     constexpr int KS = E / 16;                    // 32 x 32 x 16 steps
+    constexpr int PPK = 16 / KS;                  // epilogue positions per step
     constexpr int RB = E * 2 + 16;                // LDS bytes per library row (padded)
     constexpr int PIECES = E / 8;                 // 16-byte pieces per row
     constexpr int NW = 8;                         // waves
     constexpr int NI = 128 / NW;                  // rows (direct loads) per wave per block
     static_assert(PIECES <= 64 && NI < 64, "one row per load, vmcnt range");
+    static_assert(KS * PPK == 16, "E in {64, 128, 256}");
     __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * RB];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t c0 = max(r0, tile_lo[tile]);
     const int64_t c1 = min(r0 + kCollectChunk, tile_hi[tile]);
     if (c0 >= c1) return;
-    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 3, wn = w >> 2;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
     const int nblk = (int)((c1 - c0 + 127) / 128);
 
@@ -321,24 +326,29 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         }
     };
 
-    // this lane's query column: epilogue state (32-bit rows: the library has
-    // fewer than 2^31 rows) and B operands
-    const int col = wn * 32 + (l & 31);
-    const int64_t p = p0 + col;
-    const bool qok = p < q_end;
-    uint32_t qlo = 0, qhi = 0;
-    float qthr = INFINITY;
-    if (qok) {
-        const uint32_t qi = qperm[p];
-        qlo = (uint32_t)lo[qi];
-        qhi = (uint32_t)hi[qi];
-        qthr = thr[p];
-    }
-    bf16x8 bq[KS];
-    {
+    // this lane's two query columns: epilogue state (32-bit rows: the library
+    // has fewer than 2^31 rows) and B operands
+    int col[2];
+    bool qok[2];
+    uint32_t qlo[2], qhi[2];
+    float qthr[2];
+    bf16x8 bq[2][KS];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        col[j] = wn * 64 + j * 32 + (l & 31);
+        const int64_t p = p0 + col[j];
+        qok[j] = p < q_end;
+        qlo[j] = qhi[j] = 0;
+        qthr[j] = INFINITY;
+        if (qok[j]) {
+            const uint32_t qi = qperm[p];
+            qlo[j] = (uint32_t)lo[qi];
+            qhi[j] = (uint32_t)hi[qi];
+            qthr[j] = thr[p];
+        }
         const uint16_t* qrow = q_sorted + (size_t)min(p, q_end - 1) * E + 8 * (l >> 5);
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk) bq[kk] = *(const bf16x8*)(qrow + kk * 16);
+        for (int kk = 0; kk < KS; ++kk) bq[j][kk] = *(const bf16x8*)(qrow + kk * 16);
     }
     const uint32_t e1 = (uint32_t)c1;
     // The B operands are in registers before the pipeline starts, so that no
@@ -351,18 +361,17 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // the wave's LDS hit list and its flush to the per-query global buffers
     uint32_t wcount = 0;  // wave-uniform
     const int64_t qbase = tile * kTileQ;  // pass slot of the tile's first query
-    // one hit straight to the global buffer (score key << 32 | sorted row v)
+    // one hit straight to the global buffer (score key << 32 | sorted row:
+    // the select kernel turns rows into library indices)
     auto put = [&](int64_t qs, uint64_t v) {
         const uint32_t slot = atomicAdd(count + qs, 1u);
-        if (slot < (uint32_t)kCapacity)
-            buf[(size_t)qs * kCapacity + slot] =
-                (v & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
+        if (slot < (uint32_t)kCapacity) buf[(size_t)qs * kCapacity + slot] = v;
     };
     // the wave's list to the global buffers, four entries per lane at a time
-    // so that their atomics and lookups are in flight together
+    // so that their atomics are in flight together
     auto flush = [&]() {
         for (uint32_t e0 = 0; e0 < wcount; e0 += 256) {
-            uint32_t slot[4], orig[4];
+            uint32_t slot[4];
             int64_t qs[4];
             uint64_t v[4];
 #pragma unroll
@@ -374,87 +383,106 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                orig[u] = slot[u] < (uint32_t)kCapacity ? lib_orig[(uint32_t)v[u]] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (slot[u] < (uint32_t)kCapacity)
-                    buf[(size_t)qs[u] * kCapacity + slot[u]] =
-                        (v[u] & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - orig[u]);
+                if (slot[u] < (uint32_t)kCapacity) buf[(size_t)qs[u] * kCapacity + slot[u]] = v[u];
         }
         wcount = 0;
     };
-
-    for (int b = 0; b < nblk; ++b) {
-        // block b has landed: the loads of block b + 1 (if any) may stay in flight
-        if (b + 1 < nblk)
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(NI));
-        else
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-        __syncthreads();
-        const uint8_t* Ar = sA[b & 1] + (wr * 64 + (l & 31)) * RB + 16 * (l >> 5);
-        f32x16 acc[2];
-        acc[0] = acc[1] = f32x16{0};
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const bf16x8 av = *(const bf16x8*)(Ar + i * 32 * RB + kk * 32);
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[kk], acc[i], 0, 0, 0);
+    // append the hits of one position of query tile j (m: the wave's hit
+    // mask, uniform)
+    auto append = [&](uint64_t m, bool ok, float sc, uint32_t g, int j) {
+        const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
+        if (wcount + 64 <= kWaveList) {
+            // the sorted row: its library index is looked up by the select
+            // kernel, so no global load (and no vmcnt wait, which would also
+            // drain the prefetch) happens in this kernel
+            if (ok) {
+                const uint32_t pos =
+                    wcount + __builtin_amdgcn_mbcnt_hi(
+                                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                s_key[w][pos] = v;
+                s_col[w][pos] = (uint8_t)col[j];
             }
+            wcount += (uint32_t)__popcll(m);
+        } else if (ok) {  // list full inside a dense block: direct
+            put(qbase + col[j], v);
         }
-        __syncthreads();  // every wave is done reading sA[b & 1]
-        if (b + 2 < nblk) issue(b + 2);
+    };
 
-        // the lane's rows are gl + off, off in [0, 59]; all inside when the
-        // window and the chunk cover [gl, gl + 60]
-        const uint32_t gl = (uint32_t)(c0 + (int64_t)b * 128) + wr * 64 + 4 * (l >> 5);
-        const bool inside = gl >= qlo && gl + 61 <= qhi && gl + 61 <= e1;
-        // append the hits of one position (m: the wave's hit mask, uniform)
-        auto append = [&](uint64_t m, bool ok, float sc, uint32_t g) {
-            const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
-            if (wcount + 64 <= kWaveList) {
-                // the sorted row for now: its library index is looked up at the
-                // flush, so no global load (and no vmcnt wait, which would also
-                // drain the prefetch) happens here
-                if (ok) {
-                    const uint32_t pos =
-                        wcount + __builtin_amdgcn_mbcnt_hi(
-                                     (uint32_t)(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    s_key[w][pos] = v;
-                    s_col[w][pos] = (uint8_t)col;
+    // Accumulator register r of query tile j holds row gl + 8 (r / 4) + r % 4
+    // with gl = the block's first row + 32 wr + 4 (l / 32): offsets 0 .. 27.
+    f32x16 acc[2], prev[2];
+    bool have_prev = false, prev_fast = false;
+    uint32_t gl_prev = 0;
+    for (int b = 0; b <= nblk; ++b) {
+        if (b < nblk) {
+            // block b has landed: the loads of block b + 1 (if any) may stay in flight
+            if (b + 1 < nblk)
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(NI));
+            else
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            __syncthreads();
+            prev[0] = acc[0];
+            prev[1] = acc[1];
+            acc[0] = acc[1] = f32x16{0};
+            const uint8_t* Ar = sA[b & 1] + (wr * 32 + (l & 31)) * RB + 16 * (l >> 5);
+            if (have_prev && prev_fast) {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    const bf16x8 av = *(const bf16x8*)(Ar + kk * 32);
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[0][kk], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[1][kk], acc[1], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < PPK; ++q) {
+                        const int r = kk * PPK + q;
+                        const uint32_t g = gl_prev + (uint32_t)(8 * (r >> 2) + (r & 3));
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const float sc = prev[j][r];
+                            const uint64_t m = __ballot(sc >= qthr[j]);
+                            if (m != 0) append(m, sc >= qthr[j], sc, g, j);
+                        }
+                    }
                 }
-                wcount += (uint32_t)__popcll(m);
-            } else if (ok) {  // list full inside a dense block: direct
-                put(qbase + col, v);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    const bf16x8 av = *(const bf16x8*)(Ar + kk * 32);
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[0][kk], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[1][kk], acc[1], 0, 0, 0);
+                }
             }
-        };
-        if (__ballot(!inside && qok) == 0) {
-            // every lane's 60 rows lie inside its window: one compare per pair
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float sc = acc[i][r];
-                    const uint64_t m = __ballot(sc >= qthr);
-                    if (m != 0)
-                        append(m, sc >= qthr, sc,
-                               gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3)));
-                }
+            __syncthreads();  // every wave is done reading sA[b & 1]
+            if (b + 2 < nblk) issue(b + 2);
         } else {
-            // some lane's window or the chunk ends inside this block
+            prev[0] = acc[0];
+            prev[1] = acc[1];
+        }
+        if (have_prev && (!prev_fast || b == nblk)) {
+            // the previous block's positions not examined above
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t g = gl_prev + (uint32_t)(8 * (r >> 2) + (r & 3));
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const uint32_t g = gl + (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3));
-                    const float sc = acc[i][r];
-                    const bool ok = sc >= qthr && g < e1 && g >= qlo && g < qhi;
+                for (int j = 0; j < 2; ++j) {
+                    const float sc = prev[j][r];
+                    const bool ok = sc >= qthr[j] &&
+                                    (prev_fast || (g < e1 && g >= qlo[j] && g < qhi[j]));
                     const uint64_t m = __ballot(ok);
-                    if (m != 0) append(m, ok, sc, g);
+                    if (m != 0) append(m, ok, sc, g, j);
                 }
+            }
         }
         if (wcount > kWaveList / 2) flush();  // wave-uniform, at most once per block
+        if (b < nblk) {
+            // block b's scores are examined during block b + 1 (or after the loop)
+            have_prev = true;
+            gl_prev = (uint32_t)(c0 + (int64_t)b * 128) + wr * 32 + 4 * (l >> 5);
+            bool inside = gl_prev + 28 <= e1;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                inside = inside && (!qok[j] || (gl_prev >= qlo[j] && gl_prev + 28 <= qhi[j]));
+            prev_fast = __ballot(!inside) == 0;
+        }
     }
     flush();
 }
@@ -468,9 +496,10 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
 constexpr int kMaxK = kCapacity / 8;  // largest k the search takes
 
 __global__ __launch_bounds__(kThreads) void select_kernel(
-    int64_t q_begin, int k, const uint32_t* __restrict__ count, const uint64_t* __restrict__ buf,
+    int64_t q_begin, int k, const uint32_t* __restrict__ count, uint64_t* __restrict__ buf,
     const float* __restrict__ thr, const uint32_t* __restrict__ qperm,
-    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t* __restrict__ shortlist,
+    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
+    const uint32_t* __restrict__ lib_orig, int64_t* __restrict__ shortlist,
     uint8_t* __restrict__ fallback)
 {
     extern __shared__ uint32_t s_hi[];  // [kCapacity] high halves of the keys
@@ -485,9 +514,17 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
     const bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
-    const uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
+    uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
     const int kk = min(k, n);  // keys kept
     if (!bad && kk > 0) {      // uniform
+        // the scoring kernel stored sorted rows: library indices now (equal
+        // scores go to the lower library index)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint64_t v = keys[i];
+            keys[i] = (v & 0xFFFFFFFF00000000ull) |
+                      (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
+        }
+        __syncthreads();
         if (n <= kMaxK) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) s_sel[i] = keys[i];
         } else {
@@ -695,16 +732,16 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const dim3 cgrid((uint32_t)tiles, (uint32_t)max_chunks);
         if (E == 256)
             collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, c->lib.orig, count, buf);
+                                                      thi, m->lib_emb, count, buf);
         else if (E == 128)
             collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, c->lib.orig, count, buf);
+                                                      thi, m->lib_emb, count, buf);
         else
             collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                     thi, m->lib_emb, c->lib.orig, count, buf);
+                                                     thi, m->lib_emb, count, buf);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
-                                                          shortlist, fallback);
+                                                          c->lib.orig, shortlist, fallback);
         rescore_kernel<<<(uint32_t)((nb + 3) / 4), kThreads, 0, s>>>(
             b0, b1, k, c->words, q_hv, qperm, shortlist, c->lib.slot, c->lib.hv, keys);
         e = hipGetLastError();
