@@ -278,7 +278,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
     const uint16_t* __restrict__ lib_emb, uint32_t* __restrict__ count,
-    uint64_t* __restrict__ buf)
+    uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks)
 {
     using namespace gemm;
     constexpr int KS = E / 16;                    // 32 x 32 x 16 steps
@@ -292,11 +292,17 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * RB];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
-    // Chunks are fixed row ranges of the sorted library (blockIdx.y), clipped
-    // to the tile's candidate range: the workgroups of all tiles that cover a
-    // chunk run together (x varies fastest) and read the same rows.
-    const int64_t tile = blockIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.y * kCollectChunk;
+    // Chunks are fixed row ranges of the sorted library, clipped to the
+    // tile's candidate range. Workgroups go to the eight XCDs in turn
+    // (workgroup i to XCD i mod 8, each with its own L2): XCD x takes chunks
+    // x, x + 8, ... and, for each, every tile, so a chunk's rows are fetched
+    // into one L2 and read there by all the tiles that cover it.
+    const int64_t wg = blockIdx.x;
+    const int64_t slot = wg >> 3;
+    const int64_t chunk = (slot / n_tiles) * 8 + (wg & 7);
+    const int64_t tile = slot % n_tiles;
+    if (chunk >= n_chunks) return;
+    const int64_t r0 = chunk * kCollectChunk;
     const int64_t c0 = max(r0, tile_lo[tile]);
     const int64_t c1 = min(r0 + kCollectChunk, tile_hi[tile]);
     if (c0 >= c1) return;
@@ -729,16 +735,22 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
-        const dim3 cgrid((uint32_t)tiles, (uint32_t)max_chunks);
+        // whole rounds of 8 chunks, so every XCD's sequence is complete
+        const int64_t cwg = tiles * ((max_chunks + 7) / 8) * 8;
+        if (cwg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
+        const uint32_t cgrid = (uint32_t)cwg;
         if (E == 256)
             collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, count, buf);
+                                                      thi, m->lib_emb, count, buf, tiles,
+                                                      max_chunks);
         else if (E == 128)
             collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, count, buf);
+                                                      thi, m->lib_emb, count, buf, tiles,
+                                                      max_chunks);
         else
             collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                     thi, m->lib_emb, count, buf);
+                                                     thi, m->lib_emb, count, buf, tiles,
+                                                     max_chunks);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
                                                           c->lib.orig, shortlist, fallback);
