@@ -41,7 +41,7 @@ namespace {
 constexpr int kSample = 8192;    // most sampled candidates per window
 constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kTileQ = 128;      // queries per collection workgroup
-constexpr int64_t kCollectChunk = 4096;  // library rows per collection workgroup
+constexpr int64_t kCollectChunk = 8192;  // library rows per collection workgroup
 constexpr int kThreads = 256;
 constexpr int64_t kFallbackRows = 512;   // window rows per wave in the exhaustive fallback
 
@@ -251,17 +251,21 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // every A operand read from LDS feeds two matrix instructions. Library rows
 // stream through two LDS buffers filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4, no staging registers) two blocks ahead of their
-// use, one padded row per half-wave load so that every A read is a base plus
-// an immediate and the 16 rows read together by a quarter-wave hit distinct
-// banks. The loads are issued from inline asm with explicit vmcnt waits: the
-// compiler would otherwise drain every outstanding LDS load before any LDS
-// read and cap the prefetch at one block.
+// use. At E = 256 one load moves two 512-byte rows (every lane busy) into a
+// pair padded by 16 bytes, and matrix row i of a wave's 32-row tile reads
+// library row 2 (i mod 16) + i / 16, so that the 16 rows read together by a
+// quarter-wave lie in 16 pairs (distinct banks); at E = 64 and 128 one load
+// moves one row, padded by 16 bytes, and matrix row i reads row i. Either
+// way every A read is a base plus an immediate. The loads are issued from
+// inline asm with explicit vmcnt waits: the compiler would otherwise drain
+// every outstanding LDS load before any LDS read and cap the prefetch at one
+// block.
 //
 // Epilogue, software-pipelined: the scores of block b - 1 are examined
 // between the matrix instructions of block b (one position per step, both
 // query tiles), so that the compares and ballots issue while the matrix core
-// works. When every lane's 28 rows of the block lie inside its windows (the
-// usual case) a position costs one compare and one ballot per tile and is
+// works. When the wave's 32 rows of the block lie inside every window of its
+// queries (the usual case) a position costs one compare and one ballot per tile and is
 // skipped unless some lane hits; otherwise the block's positions are masked
 // row by row after the matrix instructions. Hits go to the wave's own LDS
 // list at positions counted from the ballot (no atomics, no global loads),
@@ -283,13 +287,16 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     using namespace gemm;
     constexpr int KS = E / 16;                    // 32 x 32 x 16 steps
     constexpr int PPK = 16 / KS;                  // epilogue positions per step
-    constexpr int RB = E * 2 + 16;                // LDS bytes per library row (padded)
+    constexpr bool kPair = E == 256;              // two rows per direct load
+    constexpr int RB = kPair ? E * 2 : E * 2 + 16;  // LDS bytes per row (padded if single)
+    constexpr int GS = 2 * RB + 16;               // LDS bytes per padded pair of rows
     constexpr int PIECES = E / 8;                 // 16-byte pieces per row
     constexpr int NW = 8;                         // waves
-    constexpr int NI = 128 / NW;                  // rows (direct loads) per wave per block
-    static_assert(PIECES <= 64 && NI < 64, "one row per load, vmcnt range");
+    constexpr int NI = 128 / NW;                  // rows per wave per block
+    constexpr int NL = kPair ? NI / 2 : NI;       // direct loads per wave per block
+    static_assert(PIECES <= 64 && NI < 64, "whole rows per load, vmcnt range");
     static_assert(KS * PPK == 16, "E in {64, 128, 256}");
-    __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * RB];
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kPair ? 64 * GS : 128 * RB];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
     // Chunks are fixed row ranges of the sorted library, clipped to the
@@ -310,15 +317,29 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
     const int nblk = (int)((c1 - c0 + 127) / 128);
 
-    // rows [c0 + 128 b, + 128) into sA[b & 1]: load x of wave w moves row
-    // NI w + x, lane l < PIECES its piece l, to consecutive LDS bytes (the
-    // destination of a direct load is M0 + 16 x lane)
+    // rows [c0 + 128 b, + 128) into sA[b & 1] (the destination of a direct
+    // load is M0 + 16 x lane): at E = 256 load x of wave w moves pair
+    // pr = NI w / 2 + x, rows 2 pr (lanes 0 .. 31) and 2 pr + 1 (lanes
+    // 32 .. 63); otherwise load x moves row NI w + x, lane l < PIECES its
+    // piece l
     auto issue = [&](int b) {
         const int64_t mb = c0 + (int64_t)b * 128;
         const uint32_t base = (uint32_t)(uintptr_t)&sA[b & 1][0];
         const uint16_t* gbase = lib_emb + (size_t)mb * E;  // wave-uniform
         const int last = (int)min((int64_t)127, c1 - 1 - mb);  // rows past c1 repeat the last
-        if (l < PIECES) {
+        if constexpr (kPair) {
+#pragma unroll
+            for (int x = 0; x < NL; ++x) {
+                const int pr = w * NL + x;
+                const int row = 2 * pr + (l >> 5);
+                const uint32_t voff = (uint32_t)(min(row, last) * (E * 2) + (l & 31) * 16);
+                const uint32_t lds = __builtin_amdgcn_readfirstlane(base + (uint32_t)(pr * GS));
+                asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                             :
+                             : "v"(voff), "s"(gbase), "s"(lds)
+                             : "memory", "m0");
+            }
+        } else if (l < PIECES) {
 #pragma unroll
             for (int x = 0; x < NI; ++x) {
                 const int row = w * NI + x;
@@ -414,8 +435,15 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         }
     };
 
-    // Accumulator register r of query tile j holds row gl + 8 (r / 4) + r % 4
-    // with gl = the block's first row + 32 wr + 4 (l / 32): offsets 0 .. 27.
+    // Accumulator register r of query tile j holds matrix row
+    // i = 8 (r / 4) + 4 (l / 32) + r % 4 of the wave's tile, which is library
+    // row wb + i (E < 256) or wb + 2 (i % 16) + i / 16 (E = 256), wb = the
+    // block's first row + 32 wr: gl + roff(r) with gl = wb + 4 (l / 32) or
+    // wb + 8 (l / 32).
+    auto roff = [](int r) -> uint32_t {
+        return kPair ? (uint32_t)(16 * ((r >> 2) & 1) + 2 * (r & 3) + (r >> 3))
+                     : (uint32_t)(8 * (r >> 2) + (r & 3));
+    };
     f32x16 acc[2], prev[2];
     bool have_prev = false, prev_fast = false;
     uint32_t gl_prev = 0;
@@ -423,14 +451,16 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         if (b < nblk) {
             // block b has landed: the loads of block b + 1 (if any) may stay in flight
             if (b + 1 < nblk)
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm(NI));
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(NL));
             else
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
             __syncthreads();
             prev[0] = acc[0];
             prev[1] = acc[1];
             acc[0] = acc[1] = f32x16{0};
-            const uint8_t* Ar = sA[b & 1] + (wr * 32 + (l & 31)) * RB + 16 * (l >> 5);
+            const uint8_t* Ar =
+                kPair ? sA[b & 1] + (wr * 16 + (l & 15)) * GS + ((l >> 4) & 1) * RB + 16 * (l >> 5)
+                      : sA[b & 1] + (wr * 32 + (l & 31)) * RB + 16 * (l >> 5);
             if (have_prev && prev_fast) {
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
@@ -440,7 +470,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
 #pragma unroll
                     for (int q = 0; q < PPK; ++q) {
                         const int r = kk * PPK + q;
-                        const uint32_t g = gl_prev + (uint32_t)(8 * (r >> 2) + (r & 3));
+                        const uint32_t g = gl_prev + roff(r);
 #pragma unroll
                         for (int j = 0; j < 2; ++j) {
                             const float sc = prev[j][r];
@@ -467,7 +497,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             // the previous block's positions not examined above
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t g = gl_prev + (uint32_t)(8 * (r >> 2) + (r & 3));
+                const uint32_t g = gl_prev + roff(r);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     const float sc = prev[j][r];
@@ -482,11 +512,12 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         if (b < nblk) {
             // block b's scores are examined during block b + 1 (or after the loop)
             have_prev = true;
-            gl_prev = (uint32_t)(c0 + (int64_t)b * 128) + wr * 32 + 4 * (l >> 5);
-            bool inside = gl_prev + 28 <= e1;
+            const uint32_t wb = (uint32_t)(c0 + (int64_t)b * 128) + wr * 32;
+            gl_prev = wb + (kPair ? 8u : 4u) * (uint32_t)(l >> 5);
+            bool inside = wb + 32 <= e1;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                inside = inside && (!qok[j] || (gl_prev >= qlo[j] && gl_prev + 28 <= qhi[j]));
+                inside = inside && (!qok[j] || (wb >= qlo[j] && wb + 32 <= qhi[j]));
             prev_fast = __ballot(!inside) == 0;
         }
     }

@@ -339,6 +339,34 @@ def test_sampled_threshold_windows():
         s.close()
 
 
+@pytest.mark.parametrize("E", [128, 256])
+def test_shortlists_at_wider_embeddings(E):
+    """The scoring kernel's other row layouts: at E = 256 library rows sit in
+    LDS as padded pairs and matrix row i of a wave's tile is library row
+    2 (i mod 16) + i / 16; at E = 128 (and 64, above) one padded row per
+    load. Sampled and unsampled windows, with window edges inside blocks:
+    every shortlist is a valid top-k of the oracle scores, fallback queries
+    carry the exhaustive answer."""
+    s = LearnedSetup(n_ref=30000, n_query=300, seed=6, E=E)
+    try:
+        g = s.g
+        El, Eq = s.oracle_scores()
+        for k, tol in ((64, 500.0), (16, 150.0), (256, 20.0)):
+            idx, dist, fb, sl = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k, value=tol,
+                                               shortlist=True)
+            idx, dist, fb, sl = (t.cpu().numpy() for t in (idx, dist, fb, sl))
+            assert fb.mean() <= 0.05, (tol, fb.mean())
+            n = _check_shortlists(s, k, tol, idx, dist, fb, sl, El, Eq)
+            empty = sum(w.size == 0 for w in s.windows(tol))
+            assert n == g.queries.n - int(fb.sum()) - int(empty), (tol, n)
+            o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge,
+                                          s.o_q, g.queries.pmz, g.queries.charge, 0, tol)
+            f = fb.astype(bool)
+            assert np.array_equal(idx[f], o_idx[f]) and np.array_equal(dist[f], o_dist[f])
+    finally:
+        s.close()
+
+
 def test_training_raises_agreement():
     """Trained on (query, exact top-1) pairs of separate training queries,
     the model's k = 8 shortlist misses the exact top-1 of held-out queries at
