@@ -40,6 +40,10 @@ namespace {
 
 constexpr int kSample = 8192;    // most sampled candidates per window
 constexpr int kCapacity = 8192;  // buffer entries per query
+// Per-query buffer counters one per 128-byte line: the atomics of one flush
+// (entries of up to 64 queries) then spread over L2 channels instead of
+// serialising on two lines.
+constexpr int kCountStride = 32;
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 8192;  // library rows per collection workgroup
 constexpr int kThreads = 256;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // row by row after the matrix instructions. Hits go to the wave's own LDS
 // list at positions counted from the ballot (no atomics, no global loads),
 // flushed to the per-query global buffers when half full and at the end.
-constexpr int kWaveList = 256;  // LDS entries per wave
+constexpr int kWaveList = 384;  // LDS entries per wave
 
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // one hit straight to the global buffer (score key << 32 | sorted row:
     // the select kernel turns rows into library indices)
     auto put = [&](int64_t qs, uint64_t v) {
-        const uint32_t slot = atomicAdd(count + qs, 1u);
+        const uint32_t slot = atomicAdd(count + qs * kCountStride, 1u);
         if (slot < (uint32_t)kCapacity) buf[(size_t)qs * kCapacity + slot] = v;
     };
     // the wave's list to the global buffers, four entries per lane at a time
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
                 const uint32_t e = e0 + 64 * u + l;
                 qs[u] = e < wcount ? qbase + s_col[w][e] : -1;
                 v[u] = e < wcount ? s_key[w][e] : 0;
-                slot[u] = qs[u] >= 0 ? atomicAdd(count + qs[u], 1u) : 0xFFFFFFFFu;
+                slot[u] = qs[u] >= 0 ? atomicAdd(count + qs[u] * kCountStride, 1u) : 0xFFFFFFFFu;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int64_t p = q_begin + blockIdx.x;
     const uint32_t qi = qperm[p];
     const int64_t w = hi[qi] - lo[qi];
-    const uint32_t cnt = count[blockIdx.x];
+    const uint32_t cnt = count[blockIdx.x * kCountStride];
     const int n = (int)min(cnt, (uint32_t)kCapacity);
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
@@ -717,7 +721,8 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
     pl.batch = std::max<int64_t>(pl.batch, kTileQ);
     if (plan) *plan = pl;
     const int64_t tiles = pl.batch / kTileQ;
-    return al(nq * E * 2) + al(nq * 4) + al(pl.batch * 4) + al(pl.batch * (int64_t)kCapacity * 8) +
+    return al(nq * E * 2) + al(nq * 4) + al(pl.batch * 4 * kCountStride) +
+           al(pl.batch * (int64_t)kCapacity * 8) +
            2 * al(tiles * 8) + al(tiles * sizeof(SampleGrid)) + al(pl.batch * (int64_t)kSample * 4);
 }
 
@@ -738,7 +743,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     float* thr = (float*)p;
     p += al(nq * 4);
     uint32_t* count = (uint32_t*)p;
-    p += al(plan.batch * 4);
+    p += al(plan.batch * 4 * kCountStride);
     uint64_t* buf = (uint64_t*)p;
     p += al(plan.batch * (int64_t)kCapacity * 8);
     int64_t* tlo = (int64_t*)p;
@@ -764,7 +769,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         sample_scores_kernel<<<(uint32_t)tiles, 256, 0, s>>>(E, b0, b1, q_sorted, tlo, thi,
                                                              m->lib_emb, grids, S);
         threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, qperm, lo, hi, grids, S, thr);
-        zero_u32_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, count);
+        zero_u32_kernel<<<blocks_for(nb * kCountStride), kThreads, 0, s>>>(nb * kCountStride,
+                                                                           count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
         // whole rounds of 8 chunks, so every XCD's sequence is complete
         const int64_t cwg = tiles * ((max_chunks + 7) / 8) * 8;
