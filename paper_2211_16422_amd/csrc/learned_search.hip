@@ -676,22 +676,27 @@ __global__ void fallback_compact_kernel(int64_t nq, const uint8_t* __restrict__ 
     if (q < nq && fallback[q]) list[atomicAdd(count, 1u)] = (uint32_t)q;
 }
 
-// Exhaustive pass over the windows of the listed queries: unit u = (list
-// entry u / max_units, rows [lo + (u % max_units) R, + R) of its window), one
-// wave per unit, grid-stride so that a fixed launch covers any count.
+// Exhaustive pass over the windows of the listed queries: unit u = (library
+// rows [(u / n) R, + R) clipped to the window of list entry u % n), n listed
+// queries, one wave per unit, grid-stride so that a fixed launch covers any
+// count. Units are block-major: the waves that run together read the same
+// rows for different queries, so a block comes from HBM about once rather
+// than once per query.
 __global__ __launch_bounds__(kThreads) void fallback_scan_kernel(
     uint32_t words, const uint32_t* __restrict__ q_hv, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const uint32_t* __restrict__ list,
     const uint32_t* __restrict__ count, int64_t max_units, const uint32_t* __restrict__ lib_hv,
     const uint32_t* __restrict__ lib_orig, uint64_t* __restrict__ keys)
 {
-    const int64_t total = (int64_t)*count * max_units;
+    const int64_t n = (int64_t)*count;
+    const int64_t total = n * max_units;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < total;
          u += waves) {
-        const uint32_t qi = list[u / max_units];
-        const int64_t a = lo[qi] + (u % max_units) * kFallbackRows;
-        const int64_t b = min(a + (int64_t)kFallbackRows, hi[qi]);
+        const int64_t blk = u / n;
+        const uint32_t qi = list[u - blk * n];
+        const int64_t a = max(blk * kFallbackRows, lo[qi]);
+        const int64_t b = min((blk + 1) * kFallbackRows, hi[qi]);
         if (a < b)  // wave-uniform
             popc::window_rows_wave(words, qi, q_hv, (uint32_t)a, (uint32_t)b, lib_hv, lib_orig,
                                    keys);
