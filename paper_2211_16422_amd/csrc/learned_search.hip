@@ -187,6 +187,57 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
     }
 }
 
+// One round of a radix select, by the first wave of the workgroup: from the
+// 256 digit counts, the largest digit d with (keys above d) < r <= (keys at
+// or above d), the count above it and hist[d] (digit 0 when r exceeds the
+// total). Lane l sums digits 255 - 4 l .. 252 - 4 l, a wave scan orders the
+// lanes, and the first lane whose running count reaches r walks its four.
+struct RadixDigit {
+    uint32_t digit, above, eq;
+};
+__device__ RadixDigit radix_digit(const uint32_t* hist, uint32_t r)
+{
+    const int l = threadIdx.x & 63;
+    uint32_t h[4], sum = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        h[c] = hist[255 - 4 * l - c];
+        sum += h[c];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (l >= off) inc += y;
+    }
+    const uint64_t m = __ballot(inc >= r);
+    RadixDigit out;
+    if (m == 0) {
+        const uint32_t h0 = hist[0];
+        out.digit = 0;
+        out.above = __shfl(inc, 63) - h0;
+        out.eq = h0;
+        return out;
+    }
+    const int L = __ffsll((unsigned long long)m) - 1;
+    uint32_t d = 0, ab = 0, e = 0, cum = inc - sum;
+    bool found = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {  // digit 255 - 4 l - c, from the top
+        if (!found && cum + h[c] >= r) {
+            found = true;
+            d = (uint32_t)(255 - 4 * l - c);
+            ab = cum;
+            e = h[c];
+        }
+        cum += h[c];
+    }
+    out.digit = __shfl(d, L);
+    out.above = __shfl(ab, L);
+    out.eq = __shfl(e, L);
+    return out;
+}
+
 // One workgroup per query of the pass: the r-th largest of its in-window
 // sample scores (radix select over order-preserving keys, 8 bits per round),
 // with r chosen so that about kCapacity / 4 window candidates are expected
@@ -197,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
     const float* __restrict__ S, float* __restrict__ thr)
 {
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_digit, s_above;
+    __shared__ RadixDigit s_rd;
     const int64_t qp = blockIdx.x;  // position in the pass
     const int64_t p = q_begin + qp;
     const uint32_t qi = qperm[p];
@@ -218,30 +269,33 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
     const int64_t target = kCapacity / 4;
     int64_t r64 = (target * ns + w - 1) / w;
     uint32_t r = (uint32_t)(r64 < 1 ? 1 : (r64 > ns ? ns : r64));
+    // the sample keys stay in registers for the four rounds
+    constexpr int kPer = kSample / kThreads;
+    uint32_t key[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = (int)threadIdx.x + j * kThreads;
+        key[j] = i < ns ? fkey(v[i]) : 0u;
+    }
     uint32_t prefix = 0, mask = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
         for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-            const uint32_t key = fkey(v[i]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = (int)threadIdx.x + j * kThreads;
+            if (i < ns && (key[j] & mask) == prefix)
+                atomicAdd(&hist[(key[j] >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t above = 0;
-            int d = 255;
-            for (; d > 0; --d) {
-                if (above + hist[d] >= r) break;
-                above += hist[d];
-            }
-            s_digit = (uint32_t)d;
-            s_above = above;
+        if (threadIdx.x < 64) {
+            const RadixDigit rd = radix_digit(hist, r);
+            if (threadIdx.x == 0) s_rd = rd;
         }
         __syncthreads();
-        prefix |= s_digit << shift;
+        prefix |= s_rd.digit << shift;
         mask |= 255u << shift;
-        r -= s_above;
-        __syncthreads();
+        r -= s_rd.above;
     }
     if (threadIdx.x == 0) thr[p] = fkey_inv(prefix);
 }
@@ -529,24 +583,25 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
 }
 
 // One workgroup per query of the pass: the k largest keys of its buffer, in
-// descending order. When more than k candidates were kept, the k-th largest
-// key is found by a radix select (8 bits per round, high 32 bits from LDS, low
-// 32 bits, which only separate equal scores, from the buffer), the keys at or
-// above it (exactly k: keys are unique) are gathered and only those are
-// sorted (bitonic, in LDS).
+// descending order. When more than kMaxK candidates were kept, the keys stay
+// in registers; a radix select over the scores (8 bits per round, each
+// round's digit found by one wave) gives the k-th largest score and how many
+// keys share it, a second select over library indices runs only among those
+// ties when not all of them are kept, and only the k kept keys are translated
+// from sorted rows to library indices and sorted (bitonic, in LDS).
 constexpr int kMaxK = kCapacity / 8;  // largest k the search takes
 
 __global__ __launch_bounds__(kThreads) void select_kernel(
-    int64_t q_begin, int k, const uint32_t* __restrict__ count, uint64_t* __restrict__ buf,
+    int64_t q_begin, int k, const uint32_t* __restrict__ count, const uint64_t* __restrict__ buf,
     const float* __restrict__ thr, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const uint32_t* __restrict__ lib_orig, int64_t* __restrict__ shortlist,
     uint8_t* __restrict__ fallback)
 {
-    extern __shared__ uint32_t s_hi[];  // [kCapacity] high halves of the keys
     __shared__ uint64_t s_sel[kMaxK];
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_digit, s_above, s_nsel;
+    __shared__ RadixDigit s_rd;
+    __shared__ uint32_t s_nsel;
     const int64_t p = q_begin + blockIdx.x;
     const uint32_t qi = qperm[p];
     const int64_t w = hi[qi] - lo[qi];
@@ -555,64 +610,86 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
     const bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
-    uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
+    const uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
     const int kk = min(k, n);  // keys kept
-    if (!bad && kk > 0) {      // uniform
-        // the scoring kernel stored sorted rows: library indices now (equal
-        // scores go to the lower library index)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint64_t v = keys[i];
-            keys[i] = (v & 0xFFFFFFFF00000000ull) |
-                      (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
-        }
-        __syncthreads();
+    // The scoring kernel stored (score << 32 | sorted row); the result keys
+    // are (score << 32 | ~library index), so that equal scores go to the
+    // lower library index.
+    auto lib_key = [&](uint64_t v) {
+        return (v & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
+    };
+    if (!bad && kk > 0) {  // uniform
         if (n <= kMaxK) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) s_sel[i] = keys[i];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) s_sel[i] = lib_key(keys[i]);
         } else {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) s_hi[i] = (uint32_t)(keys[i] >> 32);
-            __syncthreads();
-            // radix select of the kk-th largest 64-bit key
-            uint64_t prefix = 0, mask = 0;
-            uint32_t r = (uint32_t)kk;
-            for (int shift = 56; shift >= 0; shift -= 8) {
+            constexpr int kPer = kCapacity / kThreads;
+            uint64_t kv[kPer];  // this thread's keys, in registers
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int i = (int)threadIdx.x + j * kThreads;
+                kv[j] = i < n ? keys[i] : 0ull;
+            }
+            // radix select of the kk-th largest score (high halves)
+            uint32_t prefix = 0, mask = 0, r = (uint32_t)kk, eq = 0;
+            for (int shift = 24; shift >= 0; shift -= 8) {
                 for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
                 __syncthreads();
-                for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                    // high rounds from LDS; low rounds only for keys whose high half matches
-                    const uint64_t hk = (uint64_t)s_hi[i] << 32;
-                    if (shift >= 32) {
-                        if ((hk & mask) == prefix) atomicAdd(&hist[(hk >> shift) & 255u], 1u);
-                    } else if ((hk & 0xFFFFFFFF00000000ull) == (prefix & 0xFFFFFFFF00000000ull)) {
-                        const uint64_t key = keys[i];
-                        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-                    }
+#pragma unroll
+                for (int j = 0; j < kPer; ++j) {
+                    const uint32_t h = (uint32_t)(kv[j] >> 32);
+                    if ((int)threadIdx.x + j * kThreads < n && (h & mask) == prefix)
+                        atomicAdd(&hist[(h >> shift) & 255u], 1u);
                 }
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    uint32_t above = 0;
-                    int d = 255;
-                    for (; d > 0; --d) {
-                        if (above + hist[d] >= r) break;
-                        above += hist[d];
-                    }
-                    s_digit = (uint32_t)d;
-                    s_above = above;
+                if (threadIdx.x < 64) {
+                    const RadixDigit rd = radix_digit(hist, r);
+                    if (threadIdx.x == 0) s_rd = rd;
                 }
                 __syncthreads();
-                prefix |= (uint64_t)s_digit << shift;
-                mask |= (uint64_t)255 << shift;
-                r -= s_above;
-                __syncthreads();
+                prefix |= s_rd.digit << shift;
+                mask |= 255u << shift;
+                r -= s_rd.above;
+                eq = s_rd.eq;
             }
-            // prefix is now the kk-th largest key: gather the kk keys at or above it
+            // Every key scoring above `prefix` is kept, and r of the eq keys
+            // scoring exactly `prefix`: all of them when r == eq (the usual
+            // case), else those with the r lowest library indices, found by a
+            // second radix select over ~library index among the ties only.
+            const bool all_ties = r == eq;
+            uint32_t lp = 0, lmask = 0;
+            if (!all_ties) {
+                for (int shift = 24; shift >= 0; shift -= 8) {
+                    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < kPer; ++j) {
+                        if ((int)threadIdx.x + j * kThreads < n &&
+                            (uint32_t)(kv[j] >> 32) == prefix) {
+                            const uint32_t lw = (uint32_t)lib_key(kv[j]);
+                            if ((lw & lmask) == lp) atomicAdd(&hist[(lw >> shift) & 255u], 1u);
+                        }
+                    }
+                    __syncthreads();
+                    if (threadIdx.x < 64) {
+                        const RadixDigit rd = radix_digit(hist, r);
+                        if (threadIdx.x == 0) s_rd = rd;
+                    }
+                    __syncthreads();
+                    lp |= s_rd.digit << shift;
+                    lmask |= 255u << shift;
+                    r -= s_rd.above;
+                }
+            }
+            // gather the kk kept keys, translated to library indices
             if (threadIdx.x == 0) s_nsel = 0;
             __syncthreads();
-            const uint32_t thi = (uint32_t)(prefix >> 32);
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const uint32_t h = s_hi[i];
-                if (h < thi) continue;
-                const uint64_t key = keys[i];
-                if (h > thi || key >= prefix) s_sel[atomicAdd(&s_nsel, 1u)] = key;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const uint32_t h = (uint32_t)(kv[j] >> 32);
+                if ((int)threadIdx.x + j * kThreads >= n || h < prefix) continue;
+                const uint64_t key = lib_key(kv[j]);
+                if (h > prefix || all_ties || (uint32_t)key >= lp)
+                    s_sel[atomicAdd(&s_nsel, 1u)] = key;
             }
         }
         __syncthreads();
@@ -765,7 +842,6 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     if (e != hipSuccess) return e;
     const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
     if (max_chunks > 65535) return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)kCapacity * 4;
     for (int64_t b0 = 0; b0 < nq; b0 += plan.batch) {
         const int64_t b1 = std::min(nq, b0 + plan.batch), nb = b1 - b0;
         const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
@@ -794,7 +870,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
                                                      thi, m->lib_emb, count, buf, tiles,
                                                      max_chunks);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
-        select_kernel<<<(uint32_t)nb, kThreads, lds, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
+        select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
                                                           c->lib.orig, shortlist, fallback);
         rescore_kernel<<<(uint32_t)((nb + 3) / 4), kThreads, 0, s>>>(
             b0, b1, k, c->words, q_hv, qperm, shortlist, c->lib.slot, c->lib.hv, keys);
