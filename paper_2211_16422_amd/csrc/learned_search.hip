@@ -106,8 +106,12 @@ struct SampleGrid {
     int32_t n;
 };
 
-// Scores of every query of a tile against its sample grid, on matrix cores
-// (same tiling as collect_kernel): S[q][m] = e_q . e_(row m), fp32.
+// Scores of every query of a tile against its sample grid, on matrix cores:
+// S[q][m] = e_q . e_(row m), fp32. kSampleSplit workgroups per tile take
+// 128-row steps of the grid in turn; the queries are the A operand, so that
+// each accumulator register holds 32 consecutive samples of one query and
+// the stores are contiguous.
+constexpr int kSampleSplit = 8;
 __global__ __launch_bounds__(256) void sample_scores_kernel(
     int E, int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
@@ -116,7 +120,8 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
     using namespace gemm;
     __shared__ __attribute__((aligned(16))) uint8_t sA[2][kTM * kRowBytes];
     __shared__ __attribute__((aligned(16))) uint8_t sB[2][kTN * kRowBytes];
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = blockIdx.x / kSampleSplit;
+    const int split = (int)(blockIdx.x % kSampleSplit);
     const int64_t u0 = tile_lo[tile], u1 = tile_hi[tile];
     SampleGrid gr{u0, 0, 0};
     if (u1 - u0 > kSample) {
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
         gr.sh = sh;
         gr.n = (int32_t)((u1 - gr.g0 + st - 1) >> sh);
     }
-    if (threadIdx.x == 0) grids[tile] = gr;
+    if (threadIdx.x == 0 && split == 0) grids[tile] = gr;
     if (gr.n == 0) return;  // uniform
     const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 1, wn = w >> 1;
     const int64_t p0 = q_begin + tile * kTileQ;
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
     uint8_t* sa_dst = &sA[0][0] + row0 * kRowBytes + part0 * 16;
     uint8_t* sb_dst = &sB[0][0] + row0 * kRowBytes + part0 * 16;
     float* Sq = S + (size_t)(tile * kTileQ) * kSample;
-    for (int m0 = 0; m0 < gr.n; m0 += kTM) {
+    for (int m0 = split * kTM; m0 < gr.n; m0 += kSampleSplit * kTM) {
         const int64_t mrow = gr.g0 + ((int64_t)min(m0 + row0, gr.n - 1) << gr.sh);
         const uint16_t* a_row = lib_emb + (size_t)mrow * E + part0 * 8;
         Stage st;
@@ -167,21 +172,24 @@ __global__ __launch_bounds__(256) void sample_scores_kernel(
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j],
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bv[j], av[i],
                                                                            acc[i][j], 0, 0, 0);
             }
             if (s + 1 < nk) store_stage(st, sa_dst, sb_dst, b ^ 1);
             __syncthreads();
         }
+        // register r of acc[i][j]: query wn 64 + 32 j + 8 (r / 4) + 4 (l / 32) + r % 4,
+        // sample m0 + wr 64 + 32 i + l % 32
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = wn * 64 + j * 32 + (l & 31);
+        for (int i = 0; i < 2; ++i) {
+            const int m = m0 + wr * 64 + i * 32 + (l & 31);
+            if (m >= gr.n) continue;
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int m = m0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-                    if (m < gr.n) Sq[(size_t)q * kSample + m] = acc[i][j][r];
+                    const int q = wn * 64 + j * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+                    Sq[(size_t)q * kSample + m] = acc[i][j][r];
                 }
         }
     }
@@ -847,8 +855,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
         e = launch_tile_bounds(nb, qperm + b0, lo, hi, kTileQ, tlo, thi, s);
         if (e != hipSuccess) return e;
-        sample_scores_kernel<<<(uint32_t)tiles, 256, 0, s>>>(E, b0, b1, q_sorted, tlo, thi,
-                                                             m->lib_emb, grids, S);
+        sample_scores_kernel<<<(uint32_t)(tiles * kSampleSplit), 256, 0, s>>>(
+            E, b0, b1, q_sorted, tlo, thi, m->lib_emb, grids, S);
         threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb * kCountStride), kThreads, 0, s>>>(nb * kCountStride,
                                                                            count);
