@@ -727,19 +727,31 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(
     const uint32_t qi = qperm[p];
     const uint32_t* qrow = q_hv + (size_t)qi * words;
     const int64_t* sl = shortlist + (size_t)qi * k;
+    // four entries per step, 16 lanes each: lane li of group g reads 16-byte
+    // pieces li, li + 16, ... of entry base + g, so a load instruction takes
+    // four contiguous 256-byte runs
+    const int g = l >> 4, li = l & 15;
+    const uint32_t nc = words / 4;  // 16-byte pieces per row
+    const uint4* qp = (const uint4*)qrow;
     uint64_t best = ~0ull;
-    for (int base = 0; base < k; base += 64) {
-        const int j = base + l;
+    for (int base = 0; base < k; base += 4) {
+        const int j = base + g;
         const int64_t o = j < k ? sl[j] : -1;
+        uint32_t d = 0;
         if (o >= 0) {
-            const uint32_t* rp = lib_hv + (size_t)lib_slot[o] * words;
-            uint32_t d = 0;
-            for (uint32_t c = 0; c < words; c += 4) {
-                const uint4 q4 = *(const uint4*)(qrow + c);
-                const uint4 r4 = *(const uint4*)(rp + c);
+            const uint4* rp = (const uint4*)(lib_hv + (size_t)lib_slot[o] * words);
+            for (uint32_t c = li; c < nc; c += 16) {
+                const uint4 q4 = qp[c];
+                const uint4 r4 = rp[c];
                 d += __builtin_popcount(q4.x ^ r4.x) + __builtin_popcount(q4.y ^ r4.y) +
                      __builtin_popcount(q4.z ^ r4.z) + __builtin_popcount(q4.w ^ r4.w);
             }
+        }
+        d += __shfl_xor(d, 8);
+        d += __shfl_xor(d, 4);
+        d += __shfl_xor(d, 2);
+        d += __shfl_xor(d, 1);
+        if (o >= 0) {
             const uint64_t key = ((uint64_t)d << 32) | (uint64_t)o;
             best = key < best ? key : best;
         }
