@@ -53,20 +53,30 @@ __global__ void tile_bounds_kernel(int64_t nq, int64_t n_tiles, int tile,
                                    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
                                    int64_t* __restrict__ tile_lo, int64_t* __restrict__ tile_hi)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
+    // one wave per tile: lanes stride over its queries, then a wave reduction
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (t >= n_tiles) return;  // wave-uniform
     int64_t mn = INT64_MAX, mx = 0;
     const int64_t end = min((t + 1) * (int64_t)tile, nq);
-    for (int64_t i = t * tile; i < end; ++i) {
+    for (int64_t i = t * tile + l; i < end; i += 64) {
         const uint32_t q = qperm[i];
-        if (hi[q] > lo[q]) {
-            mn = min(mn, lo[q]);
-            mx = max(mx, hi[q]);
+        const int64_t a = lo[q], b = hi[q];
+        if (b > a) {
+            mn = min(mn, a);
+            mx = max(mx, b);
         }
     }
-    if (mn == INT64_MAX) mn = mx = 0;
-    tile_lo[t] = mn;
-    tile_hi[t] = mx;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, (int64_t)__shfl_xor((long long)mn, off));
+        mx = max(mx, (int64_t)__shfl_xor((long long)mx, off));
+    }
+    if (l == 0) {
+        if (mn == INT64_MAX) mn = mx = 0;
+        tile_lo[t] = mn;
+        tile_hi[t] = mx;
+    }
 }
 
 }  // namespace
@@ -79,8 +89,8 @@ hipError_t launch_tile_bounds(int64_t nq, const uint32_t* qperm, const int64_t* 
 {
     const int64_t n_tiles = (nq + tile - 1) / tile;
     if (n_tiles <= 0) return hipSuccess;
-    tile_bounds_kernel<<<(uint32_t)((n_tiles + 255) / 256), 256, 0, s>>>(nq, n_tiles, tile, qperm,
-                                                                         lo, hi, tile_lo, tile_hi);
+    tile_bounds_kernel<<<(uint32_t)((n_tiles + 3) / 4), 256, 0, s>>>(nq, n_tiles, tile, qperm, lo,
+                                                                     hi, tile_lo, tile_hi);
     return hipGetLastError();
 }
 
