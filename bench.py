@@ -46,7 +46,7 @@ MFMA_F4_PEAK_TOPS = 10100.0  # dense fp4 (and fp6) matrix peak of MI355X, TFLOP/
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
 MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
-                    ("mfma_fp4", "ef22f2c745a8cfe3"): 2.5921e+11}
+                    ("mfma_fp4", "cee04aab8d424ae0"): 2.6084e+11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),

@@ -118,7 +118,7 @@ __device__ __forceinline__ uint32_t* orig_lds() {
 }
 
 // qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8)
-template <int F, int kSG>
+template <int F, int kSG, bool kAhead>
 __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
@@ -267,13 +267,39 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     }
     const char* bufA = lds + (S & 1) * kBuf + wr * TR * 32 * kRowBytes;
     const char* bufB = lds + (S & 1) * kBuf + MR * kRowBytes + wq * TQ * 32 * kRowBytes;
+    // kAhead: the operand words of group g + 1 are read while group g
+    // computes (the scheduling barrier keeps the compiler from sinking the
+    // reads back to their use); 24 more registers
+    uint4 pa[2][TR], pb[2][TQ];
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int i = 0; i < TR; ++i) pa[0][i] = *(const uint4*)(bufA + i * 32 * kRowBytes + roff[0]);
+#pragma unroll
+      for (int j = 0; j < TQ; ++j) pb[0][j] = *(const uint4*)(bufB + j * 32 * kRowBytes + roff[0]);
+    }
 #pragma unroll
     for (int g = 0; g < kSG; ++g) {
       uint4 ca[TR], cb[TQ];
+      if constexpr (kAhead) {
+        if (g + 1 < kSG) {
 #pragma unroll
-      for (int i = 0; i < TR; ++i) ca[i] = *(const uint4*)(bufA + i * 32 * kRowBytes + roff[g]);
+          for (int i = 0; i < TR; ++i)
+            pa[(g + 1) & 1][i] = *(const uint4*)(bufA + i * 32 * kRowBytes + roff[g + 1]);
 #pragma unroll
-      for (int j = 0; j < TQ; ++j) cb[j] = *(const uint4*)(bufB + j * 32 * kRowBytes + roff[g]);
+          for (int j = 0; j < TQ; ++j)
+            pb[(g + 1) & 1][j] = *(const uint4*)(bufB + j * 32 * kRowBytes + roff[g + 1]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < TR; ++i) ca[i] = pa[g & 1][i];
+#pragma unroll
+        for (int j = 0; j < TQ; ++j) cb[j] = pb[g & 1][j];
+      } else {
+#pragma unroll
+        for (int i = 0; i < TR; ++i) ca[i] = *(const uint4*)(bufA + i * 32 * kRowBytes + roff[g]);
+#pragma unroll
+        for (int j = 0; j < TQ; ++j) cb[j] = *(const uint4*)(bufB + j * 32 * kRowBytes + roff[g]);
+      }
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         v8i bv[TQ];
@@ -381,8 +407,10 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   }
 }
 
-// 4-group stages when D / 256 is a multiple of 4, else 2-group stages
-template <int F>
+// 4-group stages when D / 256 is a multiple of 4, else 2-group stages;
+// kAhead reads each group's operands one group early (for callers with 24
+// registers to spare)
+template <int F, bool kAhead = false>
 __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
@@ -390,9 +418,11 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
 {
   if (words % 32 == 0)
-    tile_rows_staged<F, 4>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff, keys);
+    tile_rows_staged<F, 4, kAhead>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff,
+                                   keys);
   else
-    tile_rows_staged<F, 2>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff, keys);
+    tile_rows_staged<F, 2, kAhead>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff,
+                                   keys);
 }
 
 }  // namespace mfd

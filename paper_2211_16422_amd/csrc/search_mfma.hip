@@ -242,8 +242,8 @@ __global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t 
   const int64_t a64 = max(cidx * chunk, tlo[tile]);
   const int64_t b64 = min(cidx * chunk + chunk, thi[tile]);
   if (a64 >= b64) return;
-  mfd::tile_rows<F>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64, (uint32_t)b64, lib,
-                    orig, qoff, keys);
+  mfd::tile_rows<F, true>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64, (uint32_t)b64,
+                          lib, orig, qoff, keys);
 }
 
 // The fp4 form's per-query constant Q = -3D/4 + 10 |b|_0 + 2 |b|_1 + 2 |b|_2,
