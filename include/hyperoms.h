@@ -42,7 +42,7 @@ typedef int32_t homs_status;
 #define HOMS_E_OOM (-2)         /* device or host allocation failed */
 #define HOMS_E_DEVICE (-3)      /* HIP runtime or kernel failure (sticky) */
 #define HOMS_E_STATE (-4)       /* call not valid in the context's state */
-#define HOMS_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+#define HOMS_E_UNSUPPORTED (-5) /* valid request this library version does not handle */
 
 typedef struct homs_ctx homs_ctx;
 

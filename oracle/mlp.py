@@ -2,7 +2,7 @@
 
 Float64 numpy definition of the small MLP that embeds hypervectors for the
 learned shortlist (not in the paper; the paper's search is the exhaustive
-Hamming top-1 of Section 3.4, which stays the judge):
+Hamming top-1 of Section 3.4, which remains the reference answer):
 
     x  = bipolar form of the packed hypervector (bit 0 -> +1, bit 1 -> -1)
     a1 = W1 x + b1,   h = ReLU(a1)                      (D -> H)
