@@ -153,6 +153,13 @@ __device__ __forceinline__ U4 encode_one_lsh(const uint4* __restrict__ id, uint3
     return at_least<P>(c, (W + 1u) / 2u);
 }
 
+// Spectra by size class: kClass 0 below 64 peaks, 1 from 64 to 255, 2 from
+// 256 on (wider counters). The launches write disjoint spectra; splitting
+// keeps the register count, and so the occupancy, of the common case
+// independent of the counters that larger spectra need.
+__device__ __forceinline__ int size_class(int64_t np) { return np < 64 ? 0 : np < 256 ? 1 : 2; }
+
+template <int kClass>
 __global__ __launch_bounds__(256) void encode_lsh_kernel(
     const uint4* __restrict__ id, uint32_t w4, uint32_t per_block, int64_t n,
     const int64_t* __restrict__ off, const int32_t* __restrict__ bin,
@@ -168,10 +175,11 @@ __global__ __launch_bounds__(256) void encode_lsh_kernel(
     const int64_t a = off[s], b = off[s + 1];
     const int64_t np = b - a;
     // planes for the largest weighted count: np * 256
+    if (size_class(np) != kClass) return;
     U4 r;
-    if (np < 64)
+    if constexpr (kClass == 0)
         r = encode_one_lsh<14>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
-    else if (np < 256)
+    else if constexpr (kClass == 1)
         r = encode_one_lsh<16>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
     else
         r = encode_one_lsh<32>(id, w4, lane, a, b, bin, level, n_bins, n_levels, err);
@@ -179,6 +187,7 @@ __global__ __launch_bounds__(256) void encode_lsh_kernel(
     out[(size_t)row * w4 + lane] = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
 }
 
+template <int kClass>
 __global__ __launch_bounds__(256) void encode_kernel(
     const uint4* __restrict__ id, const uint4* __restrict__ lv, uint32_t w4, uint32_t per_block,
     int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ bin,
@@ -193,15 +202,18 @@ __global__ __launch_bounds__(256) void encode_kernel(
     if (s >= n) return;
     const int64_t a = off[s], b = off[s + 1];
     const int64_t np = b - a;
+    if (size_class(np) != kClass) return;
     U4 r;
-    if (np < 64)
+    if constexpr (kClass == 0) {
         r = encode_one<6>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
-    else if (np < 256)
+    } else if constexpr (kClass == 1) {
         r = encode_one<8>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
-    else if (np < 65536)
-        r = encode_one<16>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
-    else
-        r = encode_one<32>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    } else {
+        if (np < 65536)
+            r = encode_one<16>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+        else
+            r = encode_one<32>(id, lv, w4, lane, a, b, bin, level, n_bins, n_levels, err);
+    }
     const int64_t row = slot ? (int64_t)slot[s] : s;
     out[(size_t)row * w4 + lane] = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
 }
@@ -216,16 +228,28 @@ hipError_t launch_encode(const homs_ctx* c, int64_t n, const int64_t* off, const
     const uint32_t w4 = c->words / 4;  // lanes per spectrum
     const uint32_t per_block = 256u / w4;
     const int64_t blocks = (n + per_block - 1) / per_block;
+    // one launch per size class (each returns at once for the spectra of the
+    // other classes)
     if (c->p.encoding == HOMS_ENCODING_LSH) {
-        encode_lsh_kernel<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
-            reinterpret_cast<const uint4*>(c->d_id), w4, per_block, n, off, bin, level,
-            c->n_bins, c->p.n_levels, slot, reinterpret_cast<uint4*>(out), c->d_err);
+        auto lsh = [&](auto kern) {
+            kern<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
+                reinterpret_cast<const uint4*>(c->d_id), w4, per_block, n, off, bin, level,
+                c->n_bins, c->p.n_levels, slot, reinterpret_cast<uint4*>(out), c->d_err);
+        };
+        lsh(encode_lsh_kernel<0>);
+        lsh(encode_lsh_kernel<1>);
+        lsh(encode_lsh_kernel<2>);
         return hipGetLastError();
     }
-    encode_kernel<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
-        reinterpret_cast<const uint4*>(c->d_id), reinterpret_cast<const uint4*>(c->d_level), w4,
-        per_block, n, off, bin, level, c->n_bins, c->p.n_levels, slot,
-        reinterpret_cast<uint4*>(out), c->d_err);
+    auto idl = [&](auto kern) {
+        kern<<<dim3((uint32_t)blocks), dim3(per_block * w4), 0, s>>>(
+            reinterpret_cast<const uint4*>(c->d_id), reinterpret_cast<const uint4*>(c->d_level),
+            w4, per_block, n, off, bin, level, c->n_bins, c->p.n_levels, slot,
+            reinterpret_cast<uint4*>(out), c->d_err);
+    };
+    idl(encode_kernel<0>);
+    idl(encode_kernel<1>);
+    idl(encode_kernel<2>);
     return hipGetLastError();
 }
 
