@@ -9,9 +9,9 @@ encoded once before timing (reference hypervectors are encoded once and
 reused, Section 3.3). One step = encode all query spectrum vectors (already
 resident in HBM) + open-window Hamming top-1 search of every query. The
 search is exact with every engine; the default engine computes the bipolar
-dot products on matrix cores (fp8 e4m3 +-1, fp32 accumulation, which is exact
-for these integers), and the XOR + popcount and int8 engines are timed beside
-it on the same queries.
+dot products on matrix cores (fp4 e2m1 operands encoding the bits, fp32
+accumulation, which is exact for these integers), and the fp8, XOR + popcount
+and int8 engines are timed beside it on the same queries.
 
 Prints one JSON line: comparisons/s (sum of candidate-window sizes per
 second), queries/s, the roofline of the search kernel measured with HIP
@@ -107,7 +107,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(queries would be sharded across GPUs with the library replicated); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
