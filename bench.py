@@ -613,7 +613,8 @@ def prep_device_measure(ctx, lib, l_csr, dev, host_prep_s):
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
                          "algorithmic_bytes": nbytes,
-                         "kernel": "preprocess_wave_kernel (two passes) + scan",
+                         "kernel": "preprocess_wave_kernel (one staged pass) + scan "
+                                   "+ compaction",
                          "note": "bounded by the per-spectrum rank counting in LDS "
                                  "(O(peaks^2) double compares), not by HBM"}}
 

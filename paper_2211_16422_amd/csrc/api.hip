@@ -632,7 +632,8 @@ homs_status homs_preprocess_device(homs_ctx* c, int64_t n, const int64_t* d_offs
         return fail(c, HOMS_E_INVALID, "NULL device pointer");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    if (homs_status st = ensure_workspace(c, homs::prep_device_scratch_bytes(n), s)) return st;
+    if (homs_status st = ensure_workspace(c, homs::prep_device_scratch_bytes(n, c->p.top_n), s))
+        return st;
     hipEvent_t e0 = prof_mark(c, s);
     HIP_TRY(c, homs::launch_preprocess_device(c, n, d_offsets, d_mz, d_intensity, d_out_offsets,
                                               d_out_bin, d_out_level, c->ws.ptr, s),

@@ -153,7 +153,7 @@ hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_
 
 // prep_device.hip: preprocessing of raw spectra on the device
 int prep_device_max_peaks();
-size_t prep_device_scratch_bytes(int64_t n);
+size_t prep_device_scratch_bytes(int64_t n, uint32_t top_n);
 hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t* off,
                                     const double* mz, const double* inten, int64_t* out_off,
                                     int32_t* out_bin, uint8_t* out_level, void* scratch,

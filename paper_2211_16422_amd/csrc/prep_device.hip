@@ -39,6 +39,15 @@ struct PrepArgs {
     uint32_t top_n, Q;
 };
 
+// Kernel modes: 0 counts each spectrum's entries, 1 writes them at the
+// scanned offsets, 2 (staged single pass) writes the count and the entries at
+// s * stage_cap (at most min(top_n, kPrepCap) entries per spectrum), moved to
+// their final place once the counts are scanned.
+__device__ __forceinline__ int64_t stage_cap(const PrepArgs& pa)
+{
+    return pa.top_n < (uint32_t)kPrepCap ? (int64_t)pa.top_n : (int64_t)kPrepCap;
+}
+
 // bitonic sort of s[0, P) (P a power of two) under `before`, by the workgroup
 template <typename Before>
 __device__ void bitonic(double* a_mz, double* a_in, uint32_t* a_pos, int P, Before before)
@@ -84,7 +93,7 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
         if (np > kPrepCap) {  // uniform
             if (threadIdx.x == 0) {
                 atomicOr(err, kErrPeaks);
-                if (!write) counts[s] = 0;
+                if (write != 1) counts[s] = 0;
             }
             continue;
         }
@@ -174,12 +183,11 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
                     ++u;
                 }
             }
-            if (!write) {
-                counts[s] = u;
-            } else {
+            if (write != 1) counts[s] = u;
+            if (write != 0) {
                 double smax = 0.0;
                 for (int i = 0; i < u; ++i) smax = s_in[i] > smax ? s_in[i] : smax;
-                const int64_t w0 = out_off[s];
+                const int64_t w0 = write == 2 ? s * stage_cap(pa) : out_off[s];
                 for (int i = 0; i < u; ++i) {
                     int64_t lv = 0;
                     if (smax > 0.0) {
@@ -313,11 +321,9 @@ __global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
             const double v = __shfl_xor(smax, o);
             smax = v > smax ? v : smax;
         }
-        if (!write) {
-            if (l == 0) counts[s] = u_total;
-            continue;
-        }
-        int64_t w0 = out_off[s];
+        if (write != 1 && l == 0) counts[s] = u_total;
+        if (write == 0) continue;
+        int64_t w0 = write == 2 ? s * stage_cap(pa) : out_off[s];
         for (int c = 0; c < k; c += 64) {
             const int t = c + l;
             const bool first = t < k && (t == 0 || sbin[t] != sbin[t - 1]);
@@ -343,6 +349,25 @@ __global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
     }
 }
 
+// one wave per spectrum, grid-stride
+__global__ void compact_stage_kernel(int64_t n, PrepArgs pa, const int64_t* __restrict__ counts,
+                                     const int64_t* __restrict__ out_off,
+                                     const int32_t* __restrict__ st_bin,
+                                     const uint8_t* __restrict__ st_level,
+                                     int32_t* __restrict__ out_bin, uint8_t* __restrict__ out_level)
+{
+    const int l = threadIdx.x & 63;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t cap = stage_cap(pa);
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; s < n; s += waves) {
+        const int64_t c = counts[s], o = out_off[s];
+        for (int64_t j = l; j < c; j += 64) {
+            out_bin[o + j] = st_bin[s * cap + j];
+            out_level[o + j] = st_level[s * cap + j];
+        }
+    }
+}
+
 __global__ void offsets_tail_kernel(int64_t n, const int64_t* counts, int64_t* out_off)
 {
     // out_off[0, n) holds the exclusive scan; the total closes the CSR
@@ -353,12 +378,23 @@ __global__ void offsets_tail_kernel(int64_t n, const int64_t* counts, int64_t* o
 
 int prep_device_max_peaks() { return kPrepCap; }
 
-size_t prep_device_scratch_bytes(int64_t n)
+namespace {
+constexpr size_t kStageBudget = (size_t)2 << 30;  // staged single pass up to this many bytes
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+size_t stage_bytes(int64_t n, uint32_t top_n)
+{
+    const size_t cap = top_n < (uint32_t)kPrepCap ? top_n : (uint32_t)kPrepCap;
+    return al256((size_t)n * cap * 4) + al256((size_t)n * cap);
+}
+}  // namespace
+
+size_t prep_device_scratch_bytes(int64_t n, uint32_t top_n)
 {
     size_t temp = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp, (const int64_t*)nullptr,
                                           (int64_t*)nullptr, (int)n);
-    return ((size_t)n * 8 + 255) / 256 * 256 + temp;
+    const size_t st = stage_bytes(n, top_n);
+    return al256((size_t)n * 8) + al256(temp) + (st <= kStageBudget ? st : 0);
 }
 
 hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t* off,
@@ -372,7 +408,7 @@ hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t*
     PrepArgs pa{c->p.mz_min, c->p.mz_max, c->p.bins_per_da, c->p.noise_frac, c->n_bins,
                 c->p.top_n, c->p.n_levels};
     int64_t* counts = (int64_t*)scratch;
-    void* temp = (char*)scratch + ((size_t)n * 8 + 255) / 256 * 256;
+    void* temp = (char*)scratch + al256((size_t)n * 8);
     size_t temp_bytes = 0;
     hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, counts, out_off, (int)n,
                                                     s);
@@ -380,6 +416,27 @@ hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t*
     const uint32_t grid = (uint32_t)(n < 8192 ? n : 8192);
     const int64_t wgrid64 = (n + kWaves - 1) / kWaves;
     const uint32_t wgrid = (uint32_t)(wgrid64 < 65536 ? wgrid64 : 65536);
+    if (stage_bytes(n, pa.top_n) <= kStageBudget) {
+        // one pass into the staging area, scan, move into place
+        char* st = (char*)temp + al256(temp_bytes);
+        const size_t cap = pa.top_n < (uint32_t)kPrepCap ? pa.top_n : (uint32_t)kPrepCap;
+        int32_t* st_bin = (int32_t*)st;
+        uint8_t* st_level = (uint8_t*)(st + al256((size_t)n * cap * 4));
+        preprocess_wave_kernel<<<wgrid, 64 * kWaves, 0, s>>>(2, n, off, mz, inten, pa, counts,
+                                                             out_off, st_bin, st_level);
+        preprocess_kernel<<<grid, kPrepThreads, 0, s>>>(2, n, off, mz, inten, pa, counts, out_off,
+                                                        st_bin, st_level, c->d_err);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, counts, out_off, (int)n, s);
+        if (e != hipSuccess) return e;
+        offsets_tail_kernel<<<1, 1, 0, s>>>(n, counts, out_off);
+        const int64_t cgrid64 = (n + 3) / 4;
+        compact_stage_kernel<<<(uint32_t)(cgrid64 < 65536 ? cgrid64 : 65536), 256, 0, s>>>(
+            n, pa, counts, out_off, st_bin, st_level, out_bin, out_level);
+        return hipGetLastError();
+    }
+    // two passes (count, scan, write) when the staging area would be too large
     for (int write = 0; write < 2; ++write) {
         preprocess_wave_kernel<<<wgrid, 64 * kWaves, 0, s>>>(write, n, off, mz, inten, pa, counts,
                                                              out_off, out_bin, out_level);
