@@ -111,3 +111,25 @@ def test_encode_from_raw_on_device(ctx):
     op = oracle.Params(dim=2048)
     idt, lvt = oracle.codebook(op)
     assert np.array_equal(hv, oracle.encode_raw(op, idt, lvt, q))
+
+
+def test_two_pass_path_when_staging_is_too_large():
+    """With top_n = 2,048 the staging area of 220,000 spectra (2,048 entries
+    of 5 bytes each) would exceed its 2 GB budget, so the device takes the
+    two-pass path (count, scan, write); its results must be identical too."""
+    h = _h()
+    c = h.Context(h.Params(dim=2048, top_n=2048))
+    try:
+        rng = np.random.default_rng(9)
+        n = 220000
+        counts = rng.integers(0, 5, n)
+        off = np.zeros(n + 1, dtype=np.int64)
+        off[1:] = np.cumsum(counts)
+        mz = rng.uniform(90.0, 1510.0, int(off[-1]))
+        inten = rng.uniform(0.0, 100.0, int(off[-1]))
+        want = oracle.preprocess(off, mz, inten, oracle.Params(dim=2048, top_n=2048))
+        got = _device(c, off, mz, inten)
+        _same(got, want)
+        assert c.device_errors() == 0
+    finally:
+        c.close()
