@@ -296,7 +296,7 @@ homs_status homs_cascade_search(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_h
  *  grid          workgroups of the persistent kernel (1..65535).
  *  bucket_da     precursor bucket width (Da) used to order queries into tiles.
  *  engine        how wide tiles are scored: HOMS_ENGINE_POPCOUNT,
- *                HOMS_ENGINE_MFMA_F8 (the default) or HOMS_ENGINE_MFMA_F4
+ *                HOMS_ENGINE_MFMA_F8 or HOMS_ENGINE_MFMA_F4 (the default)
  *                (all exact, see homs_search_window).
  */
 typedef struct homs_batched_config {

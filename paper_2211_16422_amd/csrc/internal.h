@@ -37,7 +37,7 @@ struct BatchedConfig {
     uint32_t narrow_group = 32;   // narrow queries per work item (multiple of 4)
     uint32_t grid = 1024;         // persistent workgroups
     double bucket_da = 0.5;       // precursor bucket width for query ordering
-    int32_t engine = HOMS_ENGINE_MFMA_F8;  // wide tiles: popcount, fp8 or fp4 matrix cores
+    int32_t engine = HOMS_ENGINE_MFMA_F4;  // wide tiles: popcount, fp8 or fp4 matrix cores
 };
 
 // A captured batched search, replayed while its arguments stay the same.
