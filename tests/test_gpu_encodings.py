@@ -67,3 +67,30 @@ def test_lsh_encoding_of_hand_spectra():
         assert np.array_equal(hv[1], idt[40] | idt[41])
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("encoding", [0, 2])
+def test_encode_every_size_class(encoding):
+    """The encode kernels run one launch per peak-count class (below 64, 64 to
+    255, 256 and more, with the widest counters from 65,536 peaks for the
+    paper's encoding): spectra of 0 to 70,000 entries (bins drawn with
+    repeats, each entry a peak) must encode bit for bit like the oracle."""
+    import paper_2211_16422_amd.hyperoms as h
+    D = 2048
+    hp = h.Params(dim=D, encoding=encoding)
+    op = oracle.Params(dim=D, encoding=encoding)
+    sizes = [0, 1, 2, 63, 64, 65, 255, 256, 257, 1000, 65535, 65536, 70000, 5, 300]
+    rng = np.random.default_rng(3)
+    ctx = h.Context(hp)
+    try:
+        idt, lvt = ctx.get_codebook()
+        off = np.zeros(len(sizes) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        bins = rng.integers(0, idt.shape[0], int(off[-1])).astype(np.int32)
+        lv = rng.integers(0, 16, int(off[-1])).astype(np.uint8)
+        got = ctx.encode_queries(*h.to_device_csr(off, bins, lv, "cuda:0"))
+        want = oracle.encode(op, idt, lvt, off, bins, lv)
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
+        assert ctx.device_errors() == 0
+    finally:
+        ctx.close()
