@@ -107,12 +107,13 @@ typedef struct homs_window {
 
 /* Search engines for homs_search_window. POPCOUNT: XOR + population count
  * on packed words (Section 3.4 with the bit packing of Section 4.1).
- * MFMA_I8 / MFMA_F8 / MFMA_F4: the same distances as H = (D - <x, y>) / 2
- * of the bipolar vectors (Section 3.3), contracted on matrix cores with int8
- * +-1 (int32 accumulate), fp8 e4m3 +-1.0 or fp4 e2m1 +-1.0 (fp32 accumulate)
- * operands expanded from the packed bits on the fly. Every partial sum is an
- * integer of magnitude <= D <= 32768, so all engines return identical
- * results. */
+ * MFMA_I8 / MFMA_F8 / MFMA_F4: the same distances from the dot products of
+ * the bipolar vectors (Section 3.3), H = (D - <x, y>) / 2, contracted on
+ * matrix cores with operands expanded from the packed bits on the fly: int8
+ * +-64 (int32 accumulate, 4096 <x, y>), fp8 e4m3 +-1.0, or fp4 e2m1 values
+ * whose per-query dot product is an exact affine function of H (fp32
+ * accumulate). Every partial sum is an integer exactly representable in its
+ * accumulator, so all engines return identical results. */
 #define HOMS_ENGINE_POPCOUNT 0
 #define HOMS_ENGINE_MFMA_I8 1
 #define HOMS_ENGINE_MFMA_F8 2
@@ -230,6 +231,13 @@ homs_status homs_library_size(const homs_ctx *ctx, int64_t *n);
 /* Copies the encoded library into d_out[n][D/32] in library-index order.
  * Asynchronous on `stream`. */
 homs_status homs_library_export(homs_ctx *ctx, uint32_t *d_out, void *stream);
+
+/* The library's sorted order (test support): d_out_orig[j] (uint32) is the
+ * library index of sorted row j, rows ordered by (charge, precursor m/z,
+ * library index) (by (precursor m/z, library index) when charge_match = 0),
+ * the order that makes every Section 3.4 candidate set one run of rows.
+ * d_out_orig holds homs_library_size() entries. Asynchronous on `stream`. */
+homs_status homs_library_order(homs_ctx *ctx, uint32_t *d_out_orig, void *stream);
 
 /*
  * Candidate ranges (Section 3.4): for each query, [d_lo[q], d_hi[q]) in the
@@ -361,13 +369,15 @@ homs_status homs_device_errors(homs_ctx *ctx, uint32_t *flags, void *stream);
 
 /*
  * Kernel timing (measurement support). While enabled, every search and
- * query-encode call records HIP events on its stream around its main kernel;
+ * encode call records HIP events on its stream around its main kernels;
  * homs_profile_read waits for those events, returns the accumulated times
  * and launch counts since the last read, and resets them.
  *  search_ms/search_launches: the Hamming search kernel (any engine);
- *  encode_ms/encode_launches: the encode kernel of homs_encode_queries;
+ *  encode_ms/encode_launches: the encode kernels of homs_encode_queries and
+ *           homs_encode_library (and the device preprocessing kernels);
  *  prep_ms: window, ordering and result kernels around the search kernel
- *           (and the query embedding of homs_search_learned);
+ *           (and the query embedding of homs_search_learned), and the
+ *           library sort of homs_encode_library;
  *  score_ms/score_launches: the matrix-core scoring kernel of
  *           homs_search_learned (one launch per pass of queries); its time is
  *           also part of search_ms.
@@ -445,6 +455,43 @@ homs_status homs_model_train_step(homs_model *model, int32_t batch, const uint32
                                   const uint32_t *d_r_hv, float tau, float lr, float *d_loss,
                                   void *stream);
 
+/* Training schedule of homs_model_train (homs_train_config_default: 2
+ * epochs, batch 1024, lr 3e-5, tau 0.02, seed 0). */
+typedef struct homs_train_config {
+    uint32_t struct_size; /* sizeof(homs_train_config) */
+    int32_t epochs;       /* passes over the pairs, 1..1000 */
+    int32_t batch;        /* pairs per step: a multiple of 32 in [32, 16384] */
+    float lr;             /* Adam learning rate, >= 0 */
+    float tau;            /* InfoNCE temperature, > 0 */
+    uint32_t reserved;
+    uint64_t seed;        /* seed of the epochs' batch order */
+} homs_train_config;
+homs_status homs_train_config_default(homs_train_config *cfg);
+
+/*
+ * Trains the model on (query, exact top-1 reference) pairs, the reference
+ * being a row of the context's encoded library (the Section 3.4 search's
+ * answer is the label). Pair i is query row d_q_hv[i] ([n][D/32], 16-byte
+ * aligned) and library index d_target_idx[i] (int64, caller's library
+ * order); a pair whose index is outside [0, library size) is skipped.
+ * Schedule: the valid pairs are ordered by their reference's place in the
+ * library's (charge, precursor m/z, library index) order, ties keeping pair
+ * order, and cut into batches of cfg->batch consecutive pairs (a last partial
+ * batch is dropped), so a batch's in-batch negatives are references of
+ * neighbouring precursors. Epoch e takes the nb batches in increasing order of
+ * key(b) = output e * nb + b (0-based) of the SplitMix64 stream seeded with
+ * cfg->seed (ties: lower b), one homs_model_train_step per batch: the weights
+ * after the call equal those after that sequence of homs_model_train_step
+ * calls on the gathered rows.
+ * Out: *out_steps = epochs * nb; d_losses (optional, device float, room for
+ * epochs * floor(n / batch)) receives each step's loss in step order.
+ * Synchronous (waits for `stream`); allocates and frees its own device
+ * buffers.
+ */
+homs_status homs_model_train(homs_model *model, int64_t n, const uint32_t *d_q_hv,
+                             const int64_t *d_target_idx, const homs_train_config *cfg,
+                             float *d_losses, int64_t *out_steps, void *stream);
+
 /* Embeds the context's encoded library (model-owned bf16 rows, sorted
  * library order). Needed before homs_search_learned and again after the
  * library or the weights change. Asynchronous; grows its buffer (a device
@@ -470,6 +517,76 @@ homs_status homs_search_learned(homs_ctx *ctx, homs_model *model, int64_t nq,
                                 const int8_t *d_q_charge, const homs_window *win, int32_t k,
                                 int64_t *d_out_idx, int32_t *d_out_dist, uint8_t *d_out_fallback,
                                 int64_t *d_out_shortlist, void *stream);
+
+/*
+ * ---- Library and model files --------------------------------------------------
+ * The paper keeps preprocessed spectra in a reusable binary file (Section 3.2)
+ * and encodes reference hypervectors once for reuse (Sections 3.3 and 4.4);
+ * these calls keep an encoded library, and a trained model, across
+ * processes. All numbers are little-endian; each file ends with a 64-bit
+ * checksum of every byte before it: h = 0xcbf29ce484222325, then for each
+ * 8-byte little-endian word w (the last one zero-padded) h = (h ^ w) *
+ * 0x100000001b3 mod 2^64.
+ *
+ * Library file (96-byte header, then the sorted library):
+ *   char magic[8] = "HOMSLIB1"; uint32 version (1), dim, n_levels, top_n,
+ *   id_flips (resolved: D/2 when the parameter was 0), charge_match,
+ *   encoding, reserved (0); double mz_min, mz_max, bins_per_da, noise_frac;
+ *   uint64 seed; uint64 codebook_hash (the checksum above over the position
+ *   table's words, then the level table's); int64 n;
+ *   uint32 orig[n] (library index of each sorted row); double pmz[n];
+ *   int8 charge[n] (0 when charge_match = 0); uint32 hv[n][D/32];
+ *   uint64 checksum.
+ * Model file (32-byte header):
+ *   char magic[8] = "HOMSMDL1"; uint32 version (1), dim; int32 hidden,
+ *   embed; int64 step (Adam steps taken); then float32 W1[hidden][D],
+ *   b1[hidden], W2[embed][hidden], b2[embed] and the Adam first and second
+ *   moments of each, in the order mW1, vW1, mb1, vb1, mW2, vW2, mb2, vb2;
+ *   uint64 checksum.
+ */
+#define HOMS_FILE_LIBRARY 1
+#define HOMS_FILE_MODEL 2
+
+/* Writes the context's encoded library to `path` (replacing the file).
+ * Synchronous; on failure no file is left behind. */
+homs_status homs_library_save(homs_ctx *ctx, const char *path);
+
+/* Replaces the context's library with the one in `path`. The file must have
+ * been written with the context's parameters and codebook (HOMS_E_INVALID
+ * otherwise, as for a damaged or inconsistent file: a checksum mismatch, a
+ * size that does not match the header, an order that is not a permutation
+ * sorted by (charge, precursor m/z, library index)); the context is then as
+ * after homs_encode_library of the same spectra. Synchronous. */
+homs_status homs_library_load(homs_ctx *ctx, const char *path);
+
+/* Writes the model (weights, Adam moments and step count) to `path`, so
+ * training can resume where it stopped. Synchronous. */
+homs_status homs_model_save(homs_model *model, const char *path);
+
+/* New model on ctx from a model file (dim must equal the context's D).
+ * Library embeddings are not stored: call homs_model_embed_library before
+ * homs_search_learned. Synchronous. */
+homs_status homs_model_load(homs_ctx *ctx, const char *path, homs_model **out);
+
+/* homs_file_inspect: what a file holds, read and checked on the host (no
+ * device needed): kind (HOMS_FILE_LIBRARY or HOMS_FILE_MODEL), version, dim;
+ * for a library n, codebook_hash and the parameters it was encoded with
+ * (other fields of params at their defaults); for a model hidden, embed and
+ * step. Verifies the size and the checksum (HOMS_E_INVALID when the file is
+ * damaged). */
+typedef struct homs_file_info {
+    uint32_t kind;
+    uint32_t version;
+    uint32_t dim;
+    int32_t hidden;
+    int32_t embed;
+    int32_t reserved;
+    int64_t n;
+    int64_t step;
+    uint64_t codebook_hash;
+    homs_params params;
+} homs_file_info;
+homs_status homs_file_inspect(const char *path, homs_file_info *out);
 
 /*
  * Measurement support: sustained rate, in 32-bit lane operations per second,

@@ -11,6 +11,7 @@
 #include "codebook.h"
 #include "internal.h"
 #include "learned.h"
+#include "persist.h"
 #include "preprocess.h"
 
 namespace {
@@ -473,10 +474,15 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     if (e == hipSuccess) e = hipMalloc(&L.slot, (size_t)n * 4);
     if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
+    hipEvent_t e0 = e == hipSuccess ? prof_mark(c, s) : nullptr;
     if (e == hipSuccess)
         e = homs::launch_library_sort(n, d_pmz, d_charge, c->p.charge_match != 0, tmp, tmp_bytes,
                                       L.orig, L.pmz, L.charge, L.slot, s);
+    hipEvent_t e1 = e == hipSuccess ? prof_mark(c, s) : nullptr;
     if (e == hipSuccess) e = homs::launch_encode(c, n, d_offsets, d_bin, d_level, L.slot, L.hv, s);
+    hipEvent_t e2 = e == hipSuccess ? prof_mark(c, s) : nullptr;
+    prof_span(c, e0, e1, homs::kProfPrep);
+    prof_span(c, e1, e2, homs::kProfEncode);
     uint32_t flags = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flags, c->d_err, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -513,6 +519,19 @@ homs_status homs_library_export(homs_ctx* c, uint32_t* d_out, void* stream)
     HIP_TRY(c, homs::launch_gather_rows(c->lib.n, c->words, c->lib.hv, c->lib.orig, d_out,
                                         (hipStream_t)stream),
             "export kernel");
+    return HOMS_OK;
+}
+
+homs_status homs_library_order(homs_ctx* c, uint32_t* d_out_orig, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (c->lib.n == 0) return HOMS_OK;
+    if (!d_out_orig) return fail(c, HOMS_E_INVALID, "d_out_orig is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipMemcpyAsync(d_out_orig, c->lib.orig, (size_t)c->lib.n * 4,
+                              hipMemcpyDeviceToDevice, (hipStream_t)stream),
+            "hipMemcpyAsync(order)");
     return HOMS_OK;
 }
 
@@ -1202,6 +1221,53 @@ homs_status homs_model_train_step(homs_model* m, int32_t batch, const uint32_t* 
     return HOMS_OK;
 }
 
+homs_status homs_train_config_default(homs_train_config* cfg)
+{
+    if (!cfg) return fail(nullptr, HOMS_E_INVALID, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(homs_train_config);
+    cfg->epochs = 2;
+    cfg->batch = 1024;
+    cfg->lr = 3e-5f;
+    cfg->tau = 0.02f;
+    cfg->seed = 0;
+    return HOMS_OK;
+}
+
+homs_status homs_model_train(homs_model* m, int64_t n, const uint32_t* d_q_hv,
+                             const int64_t* d_target_idx, const homs_train_config* cfg,
+                             float* d_losses, int64_t* out_steps, void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    if (!out_steps) return fail(c, HOMS_E_INVALID, "out_steps is NULL");
+    *out_steps = 0;
+    if (!cfg || cfg->struct_size != sizeof(homs_train_config))
+        return fail(c, HOMS_E_INVALID, "cfg is NULL or cfg.struct_size != sizeof(homs_train_config)");
+    if (cfg->epochs < 1 || cfg->epochs > 1000)
+        return fail(c, HOMS_E_INVALID, "epochs must be in [1, 1000]");
+    if (cfg->batch < 32 || cfg->batch > 16384 || cfg->batch % 32 != 0)
+        return fail(c, HOMS_E_INVALID, "batch must be a multiple of 32 in [32, 16384]");
+    if (!(cfg->tau > 0.f) || !std::isfinite(cfg->tau))
+        return fail(c, HOMS_E_INVALID, "tau must be > 0");
+    if (!(cfg->lr >= 0.f) || !std::isfinite(cfg->lr))
+        return fail(c, HOMS_E_INVALID, "lr must be >= 0");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, HOMS_E_INVALID, "n out of range");
+    if (n > 0 && (!d_q_hv || !d_target_idx))
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (d_q_hv && !aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    if (n == 0 || c->lib.n == 0) return HOMS_OK;
+    DeviceGuard g(c->device);
+    int64_t steps = 0;
+    hipError_t e = homs::model_train(m, n, d_q_hv, d_target_idx, cfg->epochs, cfg->batch, cfg->lr,
+                                     cfg->tau, cfg->seed, d_losses, &steps, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "training kernels");
+    if (steps > 0) m->weights_gen += 1;
+    *out_steps = steps;
+    return HOMS_OK;
+}
+
 homs_status homs_model_embed_library(homs_model* m, void* stream)
 {
     if (homs_status s = model_usable(m)) return s;
@@ -1306,6 +1372,397 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     prof_span(c, e0, e1, homs::kProfPrep);
     prof_span(c, e1, e2, homs::kProfSearch);
     prof_span(c, e2, e3, homs::kProfPrep);
+    return HOMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// library and model files
+
+namespace {
+
+constexpr size_t kIoChunk = (size_t)64 << 20;  // bytes staged through the host per copy
+
+// checksum of the context's position and level tables (the codebook a
+// library was encoded with)
+homs_status codebook_hash(homs_ctx* c, uint64_t* out)
+{
+    std::vector<uint32_t> id, lv;
+    try {
+        id.resize((size_t)c->n_bins * c->words);
+        lv.resize((size_t)c->p.n_levels * c->words);
+    } catch (const std::bad_alloc&) {
+        return fail(c, HOMS_E_OOM, "host allocation failed (codebook)");
+    }
+    HIP_TRY(c, hipMemcpy(id.data(), c->d_id, id.size() * 4, hipMemcpyDeviceToHost),
+            "hipMemcpy(id table)");
+    HIP_TRY(c, hipMemcpy(lv.data(), c->d_level, lv.size() * 4, hipMemcpyDeviceToHost),
+            "hipMemcpy(level table)");
+    homs::Checksum h;
+    h.update(id.data(), id.size() * 4);
+    h.update(lv.data(), lv.size() * 4);
+    *out = h.value();
+    return HOMS_OK;
+}
+
+void fill_library_header(const homs_ctx* c, homs::LibraryHeader* hd)
+{
+    std::memset(hd, 0, sizeof(*hd));
+    std::memcpy(hd->magic, homs::kLibraryMagic, 8);
+    hd->version = homs::kFileVersion;
+    hd->dim = c->p.dim;
+    hd->n_levels = c->p.n_levels;
+    hd->top_n = c->p.top_n;
+    hd->id_flips = c->p.id_flips;
+    hd->charge_match = c->p.charge_match;
+    hd->encoding = c->p.encoding;
+    hd->mz_min = c->p.mz_min;
+    hd->mz_max = c->p.mz_max;
+    hd->bins_per_da = c->p.bins_per_da;
+    hd->noise_frac = c->p.noise_frac;
+    hd->seed = c->p.seed;
+}
+
+// the bytes of a library file of n rows of W words
+int64_t library_file_bytes(int64_t n, uint32_t words)
+{
+    return (int64_t)sizeof(homs::LibraryHeader) + n * (4 + 8 + 1 + 4 * (int64_t)words) + 8;
+}
+
+int64_t model_file_bytes(int64_t D, int64_t H, int64_t E)
+{
+    return (int64_t)sizeof(homs::ModelHeader) + 3 * 4 * (H * D + H + E * H + E) + 8;
+}
+
+// device -> file through a host staging buffer
+homs_status write_device(homs_ctx* c, homs::FileWriter& f, const void* d, size_t bytes,
+                         std::vector<char>& buf)
+{
+    for (size_t off = 0; off < bytes; off += buf.size()) {
+        const size_t m = std::min(buf.size(), bytes - off);
+        HIP_TRY(c, hipMemcpy(buf.data(), (const char*)d + off, m, hipMemcpyDeviceToHost),
+                "hipMemcpy(save)");
+        if (!f.write(buf.data(), m)) return fail(c, HOMS_E_INVALID, "file write failed");
+    }
+    return HOMS_OK;
+}
+
+// file -> device through a host staging buffer
+homs_status read_device(homs_ctx* c, homs::FileReader& f, void* d, size_t bytes,
+                        std::vector<char>& buf)
+{
+    for (size_t off = 0; off < bytes; off += buf.size()) {
+        const size_t m = std::min(buf.size(), bytes - off);
+        if (!f.read(buf.data(), m)) return fail(c, HOMS_E_INVALID, "file is truncated");
+        HIP_TRY(c, hipMemcpy((char*)d + off, buf.data(), m, hipMemcpyHostToDevice),
+                "hipMemcpy(load)");
+    }
+    return HOMS_OK;
+}
+
+// host copy of the device sort key of a precursor m/z (negative values
+// reversed), so a file's row order is checked exactly as the sort made it
+uint64_t order_key_host(double x)
+{
+    uint64_t b;
+    std::memcpy(&b, &x, 8);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+}  // namespace
+
+extern "C" {
+
+homs_status homs_library_save(homs_ctx* c, const char* path)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!path) return fail(c, HOMS_E_INVALID, "path is NULL");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    homs::LibraryHeader hd;
+    fill_library_header(c, &hd);
+    if (homs_status s = codebook_hash(c, &hd.codebook_hash)) return s;
+    hd.n = c->lib.n;
+    std::vector<char> buf;
+    try {
+        buf.resize(kIoChunk);
+    } catch (const std::bad_alloc&) {
+        return fail(c, HOMS_E_OOM, "host allocation failed (staging)");
+    }
+    std::string why;
+    homs::FileWriter f;
+    if (!f.open(path, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!f.write(&hd, sizeof(hd))) return fail(c, HOMS_E_INVALID, "file write failed");
+    const size_t n = (size_t)c->lib.n;
+    for (auto part : {std::make_pair((const void*)c->lib.orig, n * 4),
+                      std::make_pair((const void*)c->lib.pmz, n * 8),
+                      std::make_pair((const void*)c->lib.charge, n),
+                      std::make_pair((const void*)c->lib.hv, n * c->words * 4)})
+        if (part.second)
+            if (homs_status s = write_device(c, f, part.first, part.second, buf)) return s;
+    if (!f.finish(&why)) return fail(c, HOMS_E_INVALID, why);
+    return HOMS_OK;
+}
+
+homs_status homs_library_load(homs_ctx* c, const char* path)
+{
+    if (homs_status s = usable(c)) return s;
+    if (!path) return fail(c, HOMS_E_INVALID, "path is NULL");
+    DeviceGuard g(c->device);
+    std::string why;
+    homs::FileReader f;
+    if (!f.open(path, &why)) return fail(c, HOMS_E_INVALID, why);
+    homs::LibraryHeader hd;
+    if (!f.read(&hd, sizeof(hd)) || std::memcmp(hd.magic, homs::kLibraryMagic, 8) != 0)
+        return fail(c, HOMS_E_INVALID, "not a library file");
+    if (hd.version != homs::kFileVersion)
+        return fail(c, HOMS_E_UNSUPPORTED, "library file version " + std::to_string(hd.version));
+    homs::LibraryHeader want;
+    fill_library_header(c, &want);
+    if (hd.dim != want.dim || hd.n_levels != want.n_levels || hd.top_n != want.top_n ||
+        hd.id_flips != want.id_flips || hd.charge_match != want.charge_match ||
+        hd.encoding != want.encoding || hd.mz_min != want.mz_min || hd.mz_max != want.mz_max ||
+        hd.bins_per_da != want.bins_per_da || hd.noise_frac != want.noise_frac ||
+        hd.seed != want.seed)
+        return fail(c, HOMS_E_INVALID, "the library was encoded with other parameters");
+    if (homs_status s = codebook_hash(c, &want.codebook_hash)) return s;
+    if (hd.codebook_hash != want.codebook_hash)
+        return fail(c, HOMS_E_INVALID, "the library was encoded with another codebook");
+    if (hd.n < 0 || hd.n >= ((int64_t)1 << 31) || f.size() != library_file_bytes(hd.n, c->words))
+        return fail(c, HOMS_E_INVALID, "library file size does not match its header");
+    const int64_t n = hd.n;
+    std::vector<uint32_t> orig;
+    std::vector<double> pmz;
+    std::vector<int8_t> charge;
+    std::vector<char> buf;
+    try {
+        orig.resize(n);
+        pmz.resize(n);
+        charge.resize(n);
+        buf.resize(kIoChunk);
+    } catch (const std::bad_alloc&) {
+        return fail(c, HOMS_E_OOM, "host allocation failed (library file)");
+    }
+    if (!f.read(orig.data(), n * 4) || !f.read(pmz.data(), n * 8) || !f.read(charge.data(), n))
+        return fail(c, HOMS_E_INVALID, "file is truncated");
+    // the order must be a permutation sorted as the library sort makes it
+    {
+        std::vector<uint8_t> seen(n, 0);
+        for (int64_t j = 0; j < n; ++j) {
+            if (orig[j] >= (uint64_t)n || seen[orig[j]])
+                return fail(c, HOMS_E_INVALID, "library file order is not a permutation");
+            seen[orig[j]] = 1;
+            if (!hd.charge_match && charge[j] != 0)
+                return fail(c, HOMS_E_INVALID, "library file has charges without charge_match");
+            if (j > 0) {
+                const uint64_t a = order_key_host(pmz[j - 1]), b = order_key_host(pmz[j]);
+                const bool ordered = charge[j - 1] != charge[j] ? charge[j - 1] < charge[j]
+                                     : a != b                 ? a < b
+                                                              : orig[j - 1] < orig[j];
+                if (!ordered) return fail(c, HOMS_E_INVALID, "library file rows are not sorted");
+            }
+        }
+    }
+    homs::Library L;
+    L.n = n;
+    const size_t orig_pad = (size_t)homs::search_mfma_row_pad();
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
+        if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
+        if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
+        if (e == hipSuccess) e = hipMalloc(&L.orig, ((size_t)n + orig_pad) * 4);
+        if (e == hipSuccess) e = hipMalloc(&L.slot, (size_t)n * 4);
+        if (e == hipSuccess) e = hipMemcpy(L.orig, orig.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(L.orig + n, 0, orig_pad * 4);
+        if (e == hipSuccess) e = hipMemcpy(L.pmz, pmz.data(), (size_t)n * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(L.charge, charge.data(), (size_t)n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = homs::launch_slots(n, L.orig, L.slot, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+        free_library(L);
+        return hip_fail(c, e, "library load");
+    }
+    if (homs_status s = read_device(c, f, L.hv, (size_t)n * c->words * 4, buf)) {
+        free_library(L);
+        return s;
+    }
+    if (!f.finish(&why)) {
+        free_library(L);
+        return fail(c, HOMS_E_INVALID, why);
+    }
+    HIP_TRY(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    free_library(c->lib);
+    drop_graph(c);
+    c->lib = L;
+    c->lib_valid = true;
+    c->lib_gen += 2;
+    return HOMS_OK;
+}
+
+homs_status homs_model_save(homs_model* m, const char* path)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    if (!path) return fail(c, HOMS_E_INVALID, "path is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    homs::ModelHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, homs::kModelMagic, 8);
+    hd.version = homs::kFileVersion;
+    hd.dim = (uint32_t)m->D;
+    hd.hidden = m->H;
+    hd.embed = m->E;
+    hd.step = m->step;
+    std::vector<char> buf;
+    try {
+        buf.resize(kIoChunk);
+    } catch (const std::bad_alloc&) {
+        return fail(c, HOMS_E_OOM, "host allocation failed (staging)");
+    }
+    std::string why;
+    homs::FileWriter f;
+    if (!f.open(path, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!f.write(&hd, sizeof(hd))) return fail(c, HOMS_E_INVALID, "file write failed");
+    const size_t n1 = (size_t)m->H * m->D, n2 = (size_t)m->E * m->H;
+    const std::pair<const float*, size_t> parts[] = {
+        {m->W1, n1}, {m->b1, (size_t)m->H}, {m->W2, n2}, {m->b2, (size_t)m->E},
+        {m->mW1, n1}, {m->vW1, n1}, {m->mb1, (size_t)m->H}, {m->vb1, (size_t)m->H},
+        {m->mW2, n2}, {m->vW2, n2}, {m->mb2, (size_t)m->E}, {m->vb2, (size_t)m->E}};
+    for (const auto& part : parts)
+        if (homs_status s = write_device(c, f, part.first, part.second * 4, buf)) return s;
+    if (!f.finish(&why)) return fail(c, HOMS_E_INVALID, why);
+    return HOMS_OK;
+}
+
+homs_status homs_model_load(homs_ctx* c, const char* path, homs_model** out)
+{
+    if (!out) return fail(nullptr, HOMS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (homs_status s = usable(c)) return s;
+    if (!path) return fail(c, HOMS_E_INVALID, "path is NULL");
+    DeviceGuard g(c->device);
+    std::string why;
+    homs::FileReader f;
+    if (!f.open(path, &why)) return fail(c, HOMS_E_INVALID, why);
+    homs::ModelHeader hd;
+    if (!f.read(&hd, sizeof(hd)) || std::memcmp(hd.magic, homs::kModelMagic, 8) != 0)
+        return fail(c, HOMS_E_INVALID, "not a model file");
+    if (hd.version != homs::kFileVersion)
+        return fail(c, HOMS_E_UNSUPPORTED, "model file version " + std::to_string(hd.version));
+    if (hd.dim != c->p.dim) return fail(c, HOMS_E_INVALID, "model dimension differs from D");
+    if (hd.hidden < 32 || hd.hidden > 8192 || hd.hidden % 32 != 0 || hd.embed < 32 ||
+        hd.embed > 4096 || hd.embed % 32 != 0 || hd.step < 0)
+        return fail(c, HOMS_E_INVALID, "invalid model shape in file");
+    if (f.size() != model_file_bytes(hd.dim, hd.hidden, hd.embed))
+        return fail(c, HOMS_E_INVALID, "model file size does not match its header");
+    const size_t n1 = (size_t)hd.hidden * hd.dim, n2 = (size_t)hd.embed * hd.hidden;
+    std::vector<float> w;
+    try {
+        w.resize(3 * (n1 + n2 + hd.hidden + hd.embed));
+    } catch (const std::bad_alloc&) {
+        return fail(c, HOMS_E_OOM, "host allocation failed (model file)");
+    }
+    if (!f.read(w.data(), w.size() * 4)) return fail(c, HOMS_E_INVALID, "file is truncated");
+    if (!f.finish(&why)) return fail(c, HOMS_E_INVALID, why);
+    float* p = w.data();
+    auto take = [&](size_t k) {
+        float* r = p;
+        p += k;
+        return r;
+    };
+    float *W1 = take(n1), *b1 = take(hd.hidden), *W2 = take(n2), *b2 = take(hd.embed);
+    homs_model* m = nullptr;
+    if (homs_status s = homs_model_create(c, hd.hidden, hd.embed, W1, b1, W2, b2, &m)) return s;
+    const std::pair<float*, size_t> moments[] = {
+        {m->mW1, n1}, {m->vW1, n1}, {m->mb1, (size_t)hd.hidden}, {m->vb1, (size_t)hd.hidden},
+        {m->mW2, n2}, {m->vW2, n2}, {m->mb2, (size_t)hd.embed}, {m->vb2, (size_t)hd.embed}};
+    for (const auto& mo : moments) {
+        hipError_t e = hipMemcpy(mo.first, take(mo.second), mo.second * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            homs_model_destroy(m);
+            return hip_fail(c, e, "hipMemcpy(model moments)");
+        }
+    }
+    m->step = hd.step;
+    *out = m;
+    return HOMS_OK;
+}
+
+homs_status homs_file_inspect(const char* path, homs_file_info* out)
+{
+    if (!path || !out) return fail(nullptr, HOMS_E_INVALID, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    std::string why;
+    homs::FileReader f;
+    if (!f.open(path, &why)) return fail(nullptr, HOMS_E_INVALID, why);
+    char magic[8];
+    if (!f.read(magic, 8)) return fail(nullptr, HOMS_E_INVALID, "not a libhyperoms file");
+    int64_t payload = 0;
+    if (std::memcmp(magic, homs::kLibraryMagic, 8) == 0) {
+        homs::LibraryHeader hd;
+        std::memcpy(hd.magic, magic, 8);
+        if (!f.read((char*)&hd + 8, sizeof(hd) - 8))
+            return fail(nullptr, HOMS_E_INVALID, "file is truncated");
+        if (hd.version != homs::kFileVersion)
+            return fail(nullptr, HOMS_E_UNSUPPORTED, "file version " + std::to_string(hd.version));
+        if (hd.dim < 512 || hd.dim > 32768 || hd.dim % 512 != 0 || hd.n < 0 ||
+            hd.n >= ((int64_t)1 << 31) || f.size() != library_file_bytes(hd.n, hd.dim / 32))
+            return fail(nullptr, HOMS_E_INVALID, "library file size does not match its header");
+        out->kind = HOMS_FILE_LIBRARY;
+        out->version = hd.version;
+        out->dim = hd.dim;
+        out->n = hd.n;
+        out->codebook_hash = hd.codebook_hash;
+        homs_params_default(&out->params);
+        out->params.dim = hd.dim;
+        out->params.n_levels = hd.n_levels;
+        out->params.top_n = hd.top_n;
+        out->params.mz_min = hd.mz_min;
+        out->params.mz_max = hd.mz_max;
+        out->params.bins_per_da = hd.bins_per_da;
+        out->params.noise_frac = hd.noise_frac;
+        out->params.id_flips = hd.id_flips;
+        out->params.charge_match = hd.charge_match;
+        out->params.seed = hd.seed;
+        out->params.encoding = hd.encoding;
+        payload = f.size() - (int64_t)sizeof(hd) - 8;
+    } else if (std::memcmp(magic, homs::kModelMagic, 8) == 0) {
+        homs::ModelHeader hd;
+        std::memcpy(hd.magic, magic, 8);
+        if (!f.read((char*)&hd + 8, sizeof(hd) - 8))
+            return fail(nullptr, HOMS_E_INVALID, "file is truncated");
+        if (hd.version != homs::kFileVersion)
+            return fail(nullptr, HOMS_E_UNSUPPORTED, "file version " + std::to_string(hd.version));
+        if (hd.hidden < 32 || hd.hidden > 8192 || hd.embed < 32 || hd.embed > 4096 ||
+            hd.dim < 512 || hd.dim > 32768 ||
+            f.size() != model_file_bytes(hd.dim, hd.hidden, hd.embed))
+            return fail(nullptr, HOMS_E_INVALID, "model file size does not match its header");
+        out->kind = HOMS_FILE_MODEL;
+        out->version = hd.version;
+        out->dim = hd.dim;
+        out->hidden = hd.hidden;
+        out->embed = hd.embed;
+        out->step = hd.step;
+        payload = f.size() - (int64_t)sizeof(hd) - 8;
+    } else {
+        return fail(nullptr, HOMS_E_INVALID, "not a libhyperoms file");
+    }
+    std::vector<char> buf;
+    try {
+        buf.resize(kIoChunk);
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, HOMS_E_OOM, "host allocation failed (staging)");
+    }
+    for (int64_t off = 0; off < payload; off += (int64_t)buf.size()) {
+        const size_t m = (size_t)std::min<int64_t>((int64_t)buf.size(), payload - off);
+        if (!f.read(buf.data(), m)) return fail(nullptr, HOMS_E_INVALID, "file is truncated");
+    }
+    if (!f.finish(&why)) return fail(nullptr, HOMS_E_INVALID, why);
     return HOMS_OK;
 }
 

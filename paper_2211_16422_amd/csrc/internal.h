@@ -92,6 +92,18 @@ hipError_t launch_encode(const homs_ctx* c, int64_t n, const int64_t* off, const
                          const uint8_t* level, const uint32_t* slot, uint32_t* out,
                          hipStream_t s);
 
+// sort_scan.hip: exclusive prefix sums (uint32_t and int64_t; in and out may
+// be the same buffer) and a stable LSD radix sort of (uint64 key, uint32
+// value) pairs over key bits [begin_bit, end_bit) (a multiple of 8 wide);
+// the sorted pairs end in the *_alt buffers when *in_alt is set on return.
+size_t scan_temp_bytes(int64_t n);
+template <typename T>
+hipError_t exclusive_scan(const T* in, T* out, int64_t n, void* temp, hipStream_t s);
+size_t radix_sort_temp_bytes(int64_t n);
+hipError_t radix_sort_pairs(int64_t n, uint64_t* keys, uint64_t* keys_alt, uint32_t* vals,
+                            uint32_t* vals_alt, int begin_bit, int end_bit, void* temp,
+                            hipStream_t s, bool* in_alt);
+
 // library.hip
 size_t library_sort_temp_bytes(int64_t n);
 hipError_t launch_library_sort(int64_t n, const double* pmz, const int8_t* charge,
@@ -100,6 +112,8 @@ hipError_t launch_library_sort(int64_t n, const double* pmz, const int8_t* charg
                                uint32_t* slot_out, hipStream_t s);
 hipError_t launch_gather_rows(int64_t n, uint32_t words, const uint32_t* src,
                               const uint32_t* orig, uint32_t* dst, hipStream_t s);
+// slot[orig[j]] = j; orig must be a permutation of [0, n)
+hipError_t launch_slots(int64_t n, const uint32_t* orig, uint32_t* slot, hipStream_t s);
 hipError_t launch_window_bounds(const homs_ctx* c, int64_t nq, const double* q_pmz,
                                 const int8_t* q_charge, int32_t kind, double value,
                                 const int8_t* kinds, const double* values, int64_t* lo,

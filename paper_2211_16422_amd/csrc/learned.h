@@ -17,6 +17,7 @@ struct homs_model {
     float *gW1 = nullptr, *gb1 = nullptr, *gW2 = nullptr, *gb2 = nullptr;
     int64_t step = 0;
     uint64_t weights_gen = 0;  // bumped by every weight change
+    float* loss_scratch = nullptr;  // device float for losses nobody asked for
     void* train_ws = nullptr;
     size_t train_ws_bytes = 0;
     void* emb_ws = nullptr;
@@ -38,8 +39,26 @@ hipError_t model_alloc(homs_model* m);
 hipError_t model_refresh_bf16(homs_model* m, hipStream_t s);
 hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_f32,
                        uint16_t* out_bf16, hipStream_t s);
+// Rows of a training batch taken through device index arrays: at `step`, row
+// r of the batch is query q_rows[perm[step] * B + r] and reference (sorted
+// library row) r_rows[perm[step] * B + r].
+struct RowSelect {
+    const uint32_t* q_rows;
+    const uint32_t* r_rows;
+    const uint32_t* perm;
+    int64_t step;
+};
+// One training step on B pairs: rows [0, B) of q_hv and r_hv, or, with sel,
+// the rows sel picks out of q_hv and r_hv.
 hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t* r_hv, float tau,
-                      float lr, bool update, float* loss, hipStream_t s);
+                      float lr, bool update, float* loss, hipStream_t s,
+                      const RowSelect* sel = nullptr);
+// The training schedule of homs_model_train (pairs ordered by their
+// reference's sorted library row, batches of B, each epoch's batch order
+// from the SplitMix64 stream of `seed`); synchronous.
+hipError_t model_train(homs_model* m, int64_t n, const uint32_t* q_hv, const int64_t* target,
+                       int epochs, int B, float lr, float tau, uint64_t seed, float* losses,
+                       int64_t* steps_out, hipStream_t s);
 
 // learned_search.hip: shortlist of k per query, exact rescoring; sets
 // fallback[q] = 1 where the shortlist could not be formed (the caller then

@@ -45,6 +45,28 @@ __global__ void expand_bits_kernel(int64_t n, uint32_t words, const uint32_t* __
     }
 }
 
+// the same expansion for the rows of one training batch taken through index
+// arrays: row r of the batch is hv[rows[perm[step] * n + r]]
+__global__ void expand_rows_kernel(int64_t n, uint32_t words, const uint32_t* __restrict__ hv,
+                                   const uint32_t* __restrict__ rows,
+                                   const uint32_t* __restrict__ perm, int64_t step,
+                                   uint16_t* __restrict__ X, int64_t ld)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * (int64_t)words) return;
+    const int64_t r = t / words;
+    const uint32_t w = (uint32_t)(t - r * words);
+    const int64_t src = (int64_t)rows[(int64_t)perm[step] * n + r];
+    const uint32_t v = hv[src * words + w];
+    uint16_t* o = X + r * ld + (int64_t)w * 32;
+#pragma unroll
+    for (int b = 0; b < 32; b += 2) {
+        const uint32_t lo = ((v >> b) & 1u) ? 0xBF80u : 0x3F80u;
+        const uint32_t hi = ((v >> (b + 1)) & 1u) ? 0xBF80u : 0x3F80u;
+        *(uint32_t*)(o + b) = lo | (hi << 16);
+    }
+}
+
 // bf16 [R][C] (ld_in) -> bf16 [C][R] (ld_out), 32 x 32 tiles through LDS
 __global__ void transpose_bf16_kernel(int R, int C, const uint16_t* __restrict__ in, int ld_in,
                                       uint16_t* __restrict__ out, int ld_out)
@@ -214,7 +236,7 @@ void model_free(homs_model* m)
                     (void*)m->vW1, (void*)m->mb1, (void*)m->vb1, (void*)m->mW2, (void*)m->vW2,
                     (void*)m->mb2, (void*)m->vb2, (void*)m->W1h, (void*)m->W2h, (void*)m->W2Th,
                     (void*)m->gW1, (void*)m->gb1, (void*)m->gW2, (void*)m->gb2, m->train_ws,
-                    m->emb_ws, (void*)m->lib_emb})
+                    m->emb_ws, (void*)m->lib_emb, (void*)m->loss_scratch})
         if (p) (void)hipFree(p);
 }
 
@@ -245,6 +267,7 @@ hipError_t model_alloc(homs_model* m)
     A((void**)&m->gb1, m->H * 4);
     A((void**)&m->gW2, n2 * 4);
     A((void**)&m->gb2, m->E * 4);
+    A((void**)&m->loss_scratch, 256);
     return e;
 }
 
@@ -327,7 +350,7 @@ size_t train_ws_bytes(const homs_model* m, int B)
 }
 
 hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t* r_hv, float tau,
-                      float lr, bool update, float* loss, hipStream_t s)
+                      float lr, bool update, float* loss, hipStream_t s, const RowSelect* sel)
 {
     const int M2 = 2 * B, D = m->D, H = m->H, E = m->E;
     const uint32_t words = (uint32_t)(D / 32);
@@ -378,9 +401,17 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
         if (err != hipSuccess) return err;   \
     } while (0)
     // forward, both towers stacked: rows [0, B) queries, [B, 2B) references
-    expand_bits_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(B, words, q_hv, X, D);
-    expand_bits_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(
-        B, words, r_hv, X + (size_t)B * D, D);
+    if (sel) {
+        expand_rows_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(
+            B, words, q_hv, sel->q_rows, sel->perm, sel->step, X, D);
+        expand_rows_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(
+            B, words, r_hv, sel->r_rows, sel->perm, sel->step, X + (size_t)B * D, D);
+    } else {
+        expand_bits_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(B, words, q_hv, X,
+                                                                                D);
+        expand_bits_kernel<<<blocks_for((int64_t)B * words), kThreads, 0, s>>>(
+            B, words, r_hv, X + (size_t)B * D, D);
+    }
     STEP(gemm_nt<kBias | kStoreF32 | kStoreBf16 | kReluBf16>(s, M2, H, D, X, D, m->W1h, D, 1.f,
                                                              m->b1, nullptr, a1, H, hb, H));
     STEP(gemm_nt<kBias | kStoreF32>(s, M2, E, H, hb, H, m->W2h, H, 1.f, m->b2, nullptr, z, E,
@@ -435,6 +466,128 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
                                                                               m->W2Th, E);
 #undef STEP
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// training schedule over (query, reference) pairs
+
+namespace {
+
+// output k (0-based) of the SplitMix64 stream started at `seed` (Steele, Lea,
+// Flood, OOPSLA 2014): the state after k + 1 increments of the golden gamma,
+// through the generator's output mix
+__device__ __forceinline__ uint64_t splitmix64_output(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// pair k -> key = sorted library row of its reference (2^32 - 1 when the
+// index is outside the library), value = k; counts the valid pairs
+__global__ void pair_keys_kernel(int64_t n, const int64_t* __restrict__ target,
+                                 const uint32_t* __restrict__ slot, int64_t nlib,
+                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                 unsigned long long* __restrict__ n_valid)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = k < n;
+    const int64_t t = in ? target[k] : -1;
+    const bool valid = t >= 0 && t < nlib;
+    if (in) {
+        keys[k] = valid ? (uint64_t)slot[t] : 0xFFFFFFFFull;
+        vals[k] = (uint32_t)k;
+    }
+    const uint64_t m = __ballot(valid);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_valid, (unsigned long long)__popcll(m));
+}
+
+// ordered pair j -> its query row and its reference's sorted library row
+__global__ void pair_rows_kernel(int64_t n, const uint64_t* __restrict__ keys,
+                                 const uint32_t* __restrict__ vals, uint32_t* __restrict__ q_rows,
+                                 uint32_t* __restrict__ r_rows)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    q_rows[j] = vals[j];
+    r_rows[j] = (uint32_t)keys[j];
+}
+
+// batch b of epoch e -> key = SplitMix64 output e * nb + b, value = b
+__global__ void epoch_keys_kernel(int64_t nb, int64_t epoch, uint64_t seed,
+                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    keys[b] = splitmix64_output(seed, (uint64_t)(epoch * nb + b));
+    vals[b] = (uint32_t)b;
+}
+
+}  // namespace
+
+hipError_t model_train(homs_model* m, int64_t n, const uint32_t* q_hv, const int64_t* target,
+                       int epochs, int B, float lr, float tau, uint64_t seed, float* losses,
+                       int64_t* steps_out, hipStream_t s)
+{
+    *steps_out = 0;
+    const homs_ctx* c = m->ctx;
+    const int64_t cap = n > 1 ? n : 1;
+    const size_t sort_tmp = radix_sort_temp_bytes(cap);
+    const size_t need = 2 * al((size_t)cap * 8) + 4 * al((size_t)cap * 4) + al(sort_tmp) + al(8);
+    char* base = nullptr;
+    hipError_t e = hipMalloc((void**)&base, need);
+    if (e != hipSuccess) return e;
+    char* p = base;
+    auto take = [&](size_t bytes) {
+        void* r = p;
+        p += al(bytes);
+        return r;
+    };
+    uint64_t* ka = (uint64_t*)take((size_t)cap * 8);
+    uint64_t* kb = (uint64_t*)take((size_t)cap * 8);
+    uint32_t* va = (uint32_t*)take((size_t)cap * 4);
+    uint32_t* vb = (uint32_t*)take((size_t)cap * 4);
+    uint32_t* q_rows = (uint32_t*)take((size_t)cap * 4);
+    uint32_t* r_rows = (uint32_t*)take((size_t)cap * 4);
+    void* tmp = take(sort_tmp);
+    unsigned long long* d_valid = (unsigned long long*)take(8);
+    unsigned long long n_valid = 0;
+    int64_t nb = 0;
+    bool alt = false;
+
+    e = hipMemsetAsync(d_valid, 0, 8, s);
+    if (e == hipSuccess && n > 0) {
+        pair_keys_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, target, c->lib.slot, c->lib.n, ka,
+                                                            va, d_valid);
+        // stable: pairs of one reference keep their input order
+        e = radix_sort_pairs(n, ka, kb, va, vb, 0, 32, tmp, s, &alt);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&n_valid, d_valid, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        nb = (int64_t)n_valid / B;
+        if (nb > 0) {
+            // invalid pairs sorted last; the last partial batch is dropped
+            pair_rows_kernel<<<blocks_for(nb * B), kThreads, 0, s>>>(
+                nb * B, alt ? kb : ka, alt ? vb : va, q_rows, r_rows);
+            e = hipGetLastError();
+        }
+    }
+    for (int ep = 0; ep < epochs && e == hipSuccess && nb > 0; ++ep) {
+        epoch_keys_kernel<<<blocks_for(nb), kThreads, 0, s>>>(nb, ep, seed, ka, va);
+        e = radix_sort_pairs(nb, ka, kb, va, vb, 0, 64, tmp, s, &alt);
+        const uint32_t* perm = alt ? vb : va;
+        for (int64_t j = 0; j < nb && e == hipSuccess; ++j) {
+            const RowSelect sel{q_rows, r_rows, perm, j};
+            e = model_step(m, B, q_hv, c->lib.hv, tau, lr, true,
+                           losses ? losses + (int64_t)ep * nb + j : m->loss_scratch, s, &sel);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(base);
+    if (e == hipSuccess) *steps_out = (int64_t)epochs * nb;
+    return e;
 }
 
 }  // namespace homs

@@ -6,9 +6,8 @@
 // two binary searches in float64. Results travel as 64-bit keys
 // (distance << 32 | library index): the smallest key is the smallest
 // distance with ties to the lowest library index, so partial results of
-// different workgroups merge with one 64-bit atomicMin.
-#include <hipcub/hipcub.hpp>
-
+// different workgroups merge with one 64-bit atomicMin. The sorts are the
+// stable radix sort of sort_scan.hip.
 #include "internal.h"
 
 namespace homs {
@@ -34,12 +33,13 @@ __global__ void make_keys_kernel(int64_t n, const double* __restrict__ pmz,
     vals[i] = (uint32_t)i;
 }
 
+// second sort key: the charge of each row in the order of the first sort
 __global__ void charge_keys_kernel(int64_t n, const int8_t* __restrict__ charge, bool use_charge,
-                                   const uint32_t* __restrict__ perm, uint8_t* __restrict__ k8)
+                                   const uint32_t* __restrict__ perm, uint64_t* __restrict__ k)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    k8[i] = use_charge ? (uint8_t)((uint8_t)charge[perm[i]] ^ 0x80u) : (uint8_t)0;
+    k[i] = use_charge ? (uint64_t)((uint8_t)charge[perm[i]] ^ 0x80u) : 0ull;
 }
 
 __global__ void scatter_sorted_kernel(int64_t n, const uint32_t* __restrict__ perm,
@@ -54,6 +54,12 @@ __global__ void scatter_sorted_kernel(int64_t n, const uint32_t* __restrict__ pe
     pmz_out[j] = pmz[i];
     charge_out[j] = use_charge ? charge[i] : (int8_t)0;
     slot[i] = (uint32_t)j;
+}
+
+__global__ void slot_kernel(int64_t n, const uint32_t* __restrict__ orig, uint32_t* __restrict__ slot)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) slot[orig[j]] = (uint32_t)j;
 }
 
 __global__ void gather_rows_kernel(int64_t n, uint32_t w4, const uint4* __restrict__ src,
@@ -176,14 +182,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t library_sort_temp_bytes(int64_t n)
 {
-    size_t cub64 = 0, cub8 = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub64, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 64);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub8, (uint8_t*)nullptr, (uint8_t*)nullptr,
-                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 8);
-    const size_t cub = cub64 > cub8 ? cub64 : cub8;
-    return align_up(cub) + 2 * align_up((size_t)n * 8) + 2 * align_up((size_t)n) +
-           align_up((size_t)n * 4);
+    return 2 * align_up((size_t)n * 8) + align_up((size_t)n * 4) + radix_sort_temp_bytes(n);
 }
 
 hipError_t launch_library_sort(int64_t n, const double* pmz, const int8_t* charge, bool use_charge,
@@ -191,38 +190,38 @@ hipError_t launch_library_sort(int64_t n, const double* pmz, const int8_t* charg
                                int8_t* charge_out, uint32_t* slot_out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    size_t cub64 = 0, cub8 = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub64, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 64);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub8, (uint8_t*)nullptr, (uint8_t*)nullptr,
-                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 8);
-    const size_t cub = cub64 > cub8 ? cub64 : cub8;
     char* p = (char*)temp;
-    void* cub_tmp = p;
-    p += align_up(cub);
     uint64_t* ka = (uint64_t*)p;
     p += align_up((size_t)n * 8);
     uint64_t* kb = (uint64_t*)p;
     p += align_up((size_t)n * 8);
-    uint8_t* ca = (uint8_t*)p;
-    p += align_up((size_t)n);
-    uint8_t* cb = (uint8_t*)p;
-    p += align_up((size_t)n);
     uint32_t* va = (uint32_t*)p;
     p += align_up((size_t)n * 4);
+    void* sort_tmp = p;
+    p += radix_sort_temp_bytes(n);
     if ((size_t)(p - (char*)temp) > temp_bytes) return hipErrorInvalidValue;
-    uint32_t* vb = slot_out;  // used as scratch before the final scatter
 
+    // stable sort by precursor m/z (8 passes: back in ka / va), then a stable
+    // pass by charge (into kb's partner ka and perm_out): ties of both keys
+    // keep library order
     make_keys_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, pmz, ka, va);
-    size_t tb = cub;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(cub_tmp, tb, ka, kb, va, vb, (int)n, 0, 64, s);
+    bool alt = false;
+    hipError_t e = radix_sort_pairs(n, ka, kb, va, slot_out, 0, 64, sort_tmp, s, &alt);
     if (e != hipSuccess) return e;
-    charge_keys_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, charge, use_charge, vb, ca);
-    tb = cub;
-    e = hipcub::DeviceRadixSort::SortPairs(cub_tmp, tb, ca, cb, vb, perm_out, (int)n, 0, 8, s);
+    if (alt) return hipErrorInvalidValue;  // an even number of passes ends in ka / va
+    charge_keys_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, charge, use_charge, va, kb);
+    e = radix_sort_pairs(n, kb, ka, va, perm_out, 0, 8, sort_tmp, s, &alt);
     if (e != hipSuccess) return e;
+    if (!alt) return hipErrorInvalidValue;  // one pass ends in ka / perm_out
     scatter_sorted_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, perm_out, pmz, charge, use_charge,
                                                              pmz_out, charge_out, slot_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_slots(int64_t n, const uint32_t* orig, uint32_t* slot, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    slot_kernel<<<blocks_for(n), kThreads, 0, s>>>(n, orig, slot);
     return hipGetLastError();
 }
 
@@ -248,26 +247,23 @@ hipError_t launch_window_bounds(const homs_ctx* c, int64_t nq, const double* q_p
     return hipGetLastError();
 }
 
-size_t query_sort_temp_bytes(int64_t nq)
-{
-    size_t cub = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (int)nq, 0, 64);
-    return align_up(cub);
-}
+size_t query_sort_temp_bytes(int64_t nq) { return radix_sort_temp_bytes(nq); }
 
 hipError_t launch_query_sort(int64_t nq, const double* q_pmz, const int8_t* q_charge,
                              bool use_charge, void* temp, size_t temp_bytes, uint64_t* keys_a,
                              uint64_t* keys_b, uint32_t* perm_a, uint32_t* perm_b,
                              uint32_t** perm_out, hipStream_t s)
 {
-    *perm_out = perm_b;
+    *perm_out = perm_a;
     if (nq <= 0) return hipSuccess;
+    if (temp_bytes < radix_sort_temp_bytes(nq)) return hipErrorInvalidValue;
     query_keys_kernel<<<blocks_for(nq), kThreads, 0, s>>>(nq, q_pmz, q_charge, use_charge, keys_a,
                                                           perm_a);
-    size_t tb = temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, tb, keys_a, keys_b, perm_a, perm_b,
-                                                      (int)nq, 0, 64, s);
+    // the charge and the upper 32 bits of the ordered m/z (relative resolution
+    // 2^-20) are enough to make tiles of neighbouring precursors
+    bool alt = false;
+    hipError_t e = radix_sort_pairs(nq, keys_a, keys_b, perm_a, perm_b, 24, 64, temp, s, &alt);
+    *perm_out = alt ? perm_b : perm_a;
     return e;
 }
 

@@ -1,5 +1,5 @@
-// Matrix-core search tile (fp8 and fp4 engines of the one-shot search and the
-// batched persistent search): scores library rows [a, b) of the sorted
+// Matrix-core search tile (int8, fp8 and fp4 engines of the one-shot search
+// and the fp8 and fp4 engines of the batched persistent search): scores library rows [a, b) of the sorted
 // library against the 256 m/z-ordered queries of tile `tile` (positions
 // tile * 256 .. in qperm, of which the first nq exist) and merges each
 // query's best (distance, library index) into keys[] with one 64-bit
@@ -9,6 +9,11 @@
 //
 // fp8: with bit 0 = +1 and bit 1 = -1 on both sides, H = (D - <x, y>) / 2,
 // and <x, y> is an integer of magnitude <= D, exact in fp32.
+//
+// int8: the same components scaled to +-64 (0x40 / 0xC0, which, like the fp8
+// bytes of +-1.0, differ only in the sign bit, so the expansion is the fp8
+// one with another constant); the int32 dot product is 4096 (D - 2H), at most
+// 2^27 in magnitude, and is shifted down by 12 before the same epilogue.
 //
 // fp4 (half the operand bytes and half the matrix cycles of fp8): the query
 // side is symmetric, component c of class m = c mod 4 being (-1)^b beta_m
@@ -33,13 +38,21 @@
 // lanes loaded their own operand rows from global memory.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace homs {
 namespace mfd {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+
+// operand formats: 0 and 4 are the fp8 e4m3 and fp4 e2m1 codes of the
+// f8f6f4 matrix instruction; kFmtI8 selects the int8 instruction
+constexpr int kFmtF8 = 0, kFmtF4 = 4, kFmtI8 = 8;
 
 constexpr int WR = 2, WQ = 4, TR = 4, TQ = 2;
 constexpr int kThreads = 64 * WR * WQ;   // 512
@@ -49,14 +62,15 @@ constexpr int kQueries = WQ * TQ * 32;   // queries per tile (256)
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
 
-// 32 packed bits -> 32 fp8 e4m3 bytes of +-1.0 (0x38 / 0xB8). Byte j of dword
-// m carries bit m + 8 j in its sign position: one shift and one v_bfi_b32
-// (bit insert of the sign into 0x38383838) per dword. This orders the
-// components of a k group differently from the packed order, but the same
-// way for both operands, which leaves every dot product unchanged. sel =
-// 0x80808080 and one = 0x38383838 are passed in VGPRs (VOP3 takes no
+// 32 packed bits -> 32 bytes of +-v whose two values differ only in the sign
+// bit: fp8 e4m3 +-1.0 (0x38 / 0xB8) or int8 +-64 (0x40 / 0xC0). Byte j of
+// dword m carries bit m + 8 j in its sign position: one shift and one
+// v_bfi_b32 (bit insert of the sign into `one`, the +v byte repeated) per
+// dword. This orders the components of a k group differently from the packed
+// order, but the same way for both operands, which leaves every dot product
+// unchanged. sel = 0x80808080 and one are passed in VGPRs (VOP3 takes no
 // literal operands here).
-__device__ __forceinline__ v8i expand_pm1_fp8(uint32_t w, uint32_t sel, uint32_t one) {
+__device__ __forceinline__ v8i expand_pm1(uint32_t w, uint32_t sel, uint32_t one) {
   v8i o;
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -101,6 +115,11 @@ __device__ __forceinline__ v8i expand_lib_fp4(uint32_t w, const Fp4Consts& k) {
   return o;
 }
 
+// dot product held in accumulator register r, exact in fp32: the fp32
+// accumulators hold it as is, the int8 ones 4096 times it
+__device__ __forceinline__ float dot_of(const v16f& a, int r) { return a[r]; }
+__device__ __forceinline__ float dot_of(const v16i& a, int r) { return (float)(a[r] >> 12); }
+
 // Stage buffers: per stage, 256 library rows and 256 query rows of kSG * 32
 // bytes. The 16-byte piece p of row r is stored at position p ^ f(r) with
 // f(r) = (r / kRPB) mod kP, so that the 16 rows read together by a quarter
@@ -117,7 +136,8 @@ __device__ __forceinline__ uint32_t* orig_lds() {
   return buf;
 }
 
-// qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8)
+// qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8
+// and int8)
 template <int F, int kSG, bool kAhead>
 __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
@@ -182,9 +202,9 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   const uint32_t SPB = words / (8 * kSG);  // stages per block
   const uint32_t nblk = (b - a + MR - 1) / MR;
   const uint32_t total = nblk * SPB;
-  uint32_t sel = 0x80808080u, one = 0x38383838u;  // fp8
+  uint32_t sel = 0x80808080u, one = F == kFmtI8 ? 0x40404040u : 0x38383838u;  // int8 / fp8
   Fp4Consts k4{0x11111111u, 0x22222222u, 0x44444444u, 0x88888888u, 0xAAAAAAAAu, 0x66666666u};
-  if constexpr (F == 0)
+  if constexpr (F != kFmtF4)
     asm volatile("" : "+v"(sel), "+v"(one));  // keep in VGPRs
   else
     asm volatile("" : "+v"(k4.c11), "+v"(k4.c22), "+v"(k4.c44), "+v"(k4.c88), "+v"(k4.cAA),
@@ -253,7 +273,8 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     roff[g] = r31 * kRowBytes + 16u * ((uint32_t)(2 * g + h) ^ ((r31 / kRPB) % kP));
 
   issue(0);
-  v16f acc[TR][TQ];
+  using Acc = typename std::conditional<F == kFmtI8, v16i, v16f>::type;
+  Acc acc[TR][TQ];
   for (uint32_t S = 0; S < total; ++S) {
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // this wave's loads of stage S
     __syncthreads();  // every wave's loads landed; stage S - 1 is fully read
@@ -263,7 +284,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 #pragma unroll
       for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TQ; ++j) acc[i][j] = v16f{0};
+        for (int j = 0; j < TQ; ++j) acc[i][j] = Acc{0};
     }
     const char* bufA = lds + (S & 1) * kBuf + wr * TR * 32 * kRowBytes;
     const char* bufB = lds + (S & 1) * kBuf + MR * kRowBytes + wq * TQ * 32 * kRowBytes;
@@ -306,23 +327,34 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 #pragma unroll
         for (int j = 0; j < TQ; ++j) {
           const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
-          if constexpr (F == 0)
-            bv[j] = expand_pm1_fp8(x, sel, one);
-          else
+          if constexpr (F == kFmtF4)
             bv[j] = expand_query_fp4(x, k4);
+          else
+            bv[j] = expand_pm1(x, sel, one);
         }
 #pragma unroll
         for (int i = 0; i < TR; ++i) {
           const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
           v8i av;
-          if constexpr (F == 0)
-            av = expand_pm1_fp8(x, sel, one);
-          else
+          if constexpr (F == kFmtF4)
             av = expand_lib_fp4(x, k4);
+          else
+            av = expand_pm1(x, sel, one);
 #pragma unroll
-          for (int j = 0; j < TQ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], F, F,
-                                                                         0, 0, 0, 0);
+          for (int j = 0; j < TQ; ++j) {
+            if constexpr (F == kFmtI8) {
+              // bytes 0-15 and 16-31 of each lane: two K = 32 halves of the
+              // same 64 components, split alike on both operands
+              const v4i a0 = {av[0], av[1], av[2], av[3]}, a1 = {av[4], av[5], av[6], av[7]};
+              const v4i b0 = {bv[j][0], bv[j][1], bv[j][2], bv[j][3]};
+              const v4i b1 = {bv[j][4], bv[j][5], bv[j][6], bv[j][7]};
+              acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc[i][j], 0, 0, 0);
+            } else {
+              acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv[j], acc[i][j], F,
+                                                                           F, 0, 0, 0, 0);
+            }
+          }
         }
       }
     }
@@ -344,11 +376,11 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
       // far looks up library indices
 #pragma unroll
       for (int j = 0; j < TQ; ++j) {
-        float m = acc[0][j][0];
+        float m = dot_of(acc[0][j], 0);
 #pragma unroll
         for (int i = 0; i < TR; ++i)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[i][j][r]);
+          for (int r = 0; r < 16; ++r) m = fmaxf(m, dot_of(acc[i][j], r));
         if (m >= need[j]) {
           uint32_t o_min = ~0u;
 #pragma unroll
@@ -359,7 +391,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
               const uint32_t ov[4] = {o4.x, o4.y, o4.z, o4.w};
 #pragma unroll
               for (int r4 = 0; r4 < 4; ++r4)
-                if (acc[i][j][4 * rg + r4] == m) o_min = min(o_min, ov[r4]);
+                if (dot_of(acc[i][j], 4 * rg + r4) == m) o_min = min(o_min, ov[r4]);
             }
           const uint32_t d = (uint32_t)(Q[j] - (int)m) >> 1;
           const uint64_t key = ((uint64_t)d << 32) | o_min;
@@ -381,7 +413,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
             const uint32_t g = g0 + r4;
 #pragma unroll
             for (int j = 0; j < TQ; ++j) {
-              const int dot = (int)acc[i][j][4 * rg + r4];
+              const int dot = (int)dot_of(acc[i][j], 4 * rg + r4);
               const uint32_t d = (uint32_t)(Q[j] - dot) >> 1;
               const bool in = (g < b) && (g >= qlo[j]) && (g < qhi[j]);
               const uint64_t key = in ? (((uint64_t)d << 32) | ov[r4]) : ~0ull;

@@ -19,7 +19,6 @@
 //
 // Two passes over the spectra: the first counts each spectrum's unique bins,
 // an exclusive scan gives the CSR offsets, the second recomputes and writes.
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
@@ -390,9 +389,7 @@ size_t stage_bytes(int64_t n, uint32_t top_n)
 
 size_t prep_device_scratch_bytes(int64_t n, uint32_t top_n)
 {
-    size_t temp = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp, (const int64_t*)nullptr,
-                                          (int64_t*)nullptr, (int)n);
+    const size_t temp = scan_temp_bytes(n);
     const size_t st = stage_bytes(n, top_n);
     return al256((size_t)n * 8) + al256(temp) + (st <= kStageBudget ? st : 0);
 }
@@ -409,10 +406,8 @@ hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t*
                 c->p.top_n, c->p.n_levels};
     int64_t* counts = (int64_t*)scratch;
     void* temp = (char*)scratch + al256((size_t)n * 8);
-    size_t temp_bytes = 0;
-    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, counts, out_off, (int)n,
-                                                    s);
-    if (e != hipSuccess) return e;
+    const size_t temp_bytes = scan_temp_bytes(n);
+    hipError_t e = hipSuccess;
     const uint32_t grid = (uint32_t)(n < 8192 ? n : 8192);
     const int64_t wgrid64 = (n + kWaves - 1) / kWaves;
     const uint32_t wgrid = (uint32_t)(wgrid64 < 65536 ? wgrid64 : 65536);
@@ -428,7 +423,7 @@ hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t*
                                                         st_bin, st_level, c->d_err);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, counts, out_off, (int)n, s);
+        e = exclusive_scan<int64_t>(counts, out_off, n, temp, s);
         if (e != hipSuccess) return e;
         offsets_tail_kernel<<<1, 1, 0, s>>>(n, counts, out_off);
         const int64_t cgrid64 = (n + 3) / 4;
@@ -445,7 +440,7 @@ hipError_t launch_preprocess_device(const homs_ctx* c, int64_t n, const int64_t*
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (!write) {
-            e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, counts, out_off, (int)n, s);
+            e = exclusive_scan<int64_t>(counts, out_off, n, temp, s);
             if (e != hipSuccess) return e;
             offsets_tail_kernel<<<1, 1, 0, s>>>(n, counts, out_off);
         }

@@ -93,6 +93,7 @@ _sig("homs_encode_queries", [_P, _i64, _P, _P, _P, _P, _P])
 _sig("homs_encode_library", [_P, _i64, _P, _P, _P, _P, _P, _P])
 _sig("homs_library_size", [_P, ctypes.POINTER(_i64)])
 _sig("homs_library_export", [_P, _P, _P])
+_sig("homs_library_order", [_P, _P, _P])
 _sig("homs_window_bounds", [_P, _i64, _P, _P, ctypes.POINTER(_Window), _P, _P, _P])
 _sig("homs_search_window", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P])
 _sig("homs_preprocess_device", [_P, _i64, _P, _P, _P, _P, _P, _P, _P])
@@ -130,7 +131,8 @@ _sig("homs_autotune_batched", [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _i32,
 EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_last_error",
             "homs_preprocess", "homs_create", "homs_destroy", "homs_generate_codebook", "homs_set_codebook",
             "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
-            "homs_library_size", "homs_library_export", "homs_window_bounds",
+            "homs_library_size", "homs_library_export", "homs_library_order",
+            "homs_window_bounds",
             "homs_search_window", "homs_cascade_search", "homs_preprocess_device",
             "homs_debug_distances",
             "homs_device_errors",
@@ -138,8 +140,10 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_batched_config_set", "homs_search_batched", "homs_autotune_batched",
             "homs_model_create", "homs_model_destroy", "homs_model_set_weights",
             "homs_model_get_weights", "homs_model_embed", "homs_model_gradients",
-            "homs_model_train_step", "homs_model_embed_library", "homs_search_learned",
-            "homs_measure_xor_popcount_rate"]
+            "homs_model_train_step", "homs_train_config_default", "homs_model_train",
+            "homs_model_embed_library", "homs_search_learned",
+            "homs_measure_xor_popcount_rate", "homs_library_save", "homs_library_load",
+            "homs_model_save", "homs_model_load", "homs_file_inspect"]
 
 _sig("homs_model_create", [_P, _i32, _i32, _P, _P, _P, _P, ctypes.POINTER(_P)])
 _sig("homs_model_destroy", [_P], None)
@@ -149,11 +153,56 @@ _sig("homs_model_embed", [_P, _i64, _P, _P, _P])
 _sig("homs_model_gradients", [_P, _i32, _P, _P, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
                               _P, _P, _P, _P, _P])
 _sig("homs_model_train_step", [_P, _i32, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P])
+
+
+class _TrainConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("tau", ctypes.c_float),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+_sig("homs_train_config_default", [ctypes.POINTER(_TrainConfig)])
+_sig("homs_model_train", [_P, _i64, _P, _P, ctypes.POINTER(_TrainConfig), _P,
+                          ctypes.POINTER(_i64), _P])
 _sig("homs_model_embed_library", [_P, _P])
 _sig("homs_search_learned", [_P, _P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P,
                              _P, _P])
 
 _sig("homs_measure_xor_popcount_rate", [_i32, ctypes.POINTER(ctypes.c_double)])
+
+FILE_LIBRARY = 1
+FILE_MODEL = 2
+
+
+class _FileInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("version", ctypes.c_uint32),
+                ("dim", ctypes.c_uint32), ("hidden", ctypes.c_int32), ("embed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("codebook_hash", ctypes.c_uint64), ("params", _Params)]
+
+
+_sig("homs_library_save", [_P, ctypes.c_char_p])
+_sig("homs_library_load", [_P, ctypes.c_char_p])
+_sig("homs_model_save", [_P, ctypes.c_char_p])
+_sig("homs_model_load", [_P, ctypes.c_char_p, ctypes.POINTER(_P)])
+_sig("homs_file_inspect", [ctypes.c_char_p, ctypes.POINTER(_FileInfo)])
+
+
+def file_info(path: str) -> dict:
+    """homs_file_inspect: what a library or model file holds (host only; checks
+    the size and the checksum)."""
+    fi = _FileInfo()
+    _check(_lib.homs_file_inspect(os.fsencode(path), ctypes.byref(fi)))
+    out = {"kind": fi.kind, "version": fi.version, "dim": fi.dim, "hidden": fi.hidden,
+           "embed": fi.embed, "n": fi.n, "step": fi.step, "codebook_hash": fi.codebook_hash}
+    if fi.kind == FILE_LIBRARY:
+        p = fi.params
+        out["params"] = {"dim": p.dim, "n_levels": p.n_levels, "top_n": p.top_n,
+                         "mz_min": p.mz_min, "mz_max": p.mz_max, "bins_per_da": p.bins_per_da,
+                         "noise_frac": p.noise_frac, "id_flips": p.id_flips,
+                         "charge_match": p.charge_match, "seed": p.seed,
+                         "encoding": p.encoding}
+    return out
 
 
 def measure_xor_popcount_rate(device: int = 0) -> float:
@@ -354,6 +403,22 @@ class Context:
                                           _stream(self.device)))
         return out
 
+    def library_save(self, path: str):
+        """homs_library_save: the encoded library to a file."""
+        self._ck(_lib.homs_library_save(self._h, os.fsencode(path)))
+
+    def library_load(self, path: str):
+        """homs_library_load: the library of a file written with these parameters."""
+        self._ck(_lib.homs_library_load(self._h, os.fsencode(path)))
+
+    def library_order(self):
+        """homs_library_order: library index of each sorted row (uint32 as int32)."""
+        import torch
+        out = torch.empty(max(self.library_size(), 1), dtype=torch.int32, device=self.device)
+        self._ck(_lib.homs_library_order(self._h, _dptr(out, torch.int32, "out", self.device),
+                                         _stream(self.device)))
+        return out[:self.library_size()]
+
     # --- search
     @staticmethod
     def _win(kind: int, value: float) -> _Window:
@@ -536,6 +601,31 @@ def to_device_csr(off, bins, levels, device):
 WEIGHT_NAMES = ("W1", "b1", "W2", "b2")
 
 
+def sketch_weights(dim: int, hidden: int, embed: int, seed: int = 0) -> dict:
+    """Weights under which the network needs no training: it computes a
+    signed block-sum sketch (CountSketch) of the bipolar hypervector. The D
+    components are dealt at random into `embed` blocks of D / embed, each
+    component with a random sign, z_j = sum over block j of s_d x_d; hidden
+    units 2j and 2j + 1 carry ReLU(z_j) and ReLU(-z_j) and W2 takes their
+    difference, so z is the sketch exactly (integers of magnitude <= D /
+    embed, exact in bfloat16). The shortlist score is the cosine of the two
+    sketches: a training-free shortlist at the same embedding width."""
+    if hidden < 2 * embed or dim % embed:
+        raise ValueError("needs hidden >= 2 * embed and embed dividing dim")
+    rng = np.random.default_rng(seed)
+    comp = rng.permutation(dim).reshape(embed, dim // embed)
+    sign = rng.choice(np.array([-1.0, 1.0], np.float32), size=(embed, dim // embed))
+    W1 = np.zeros((hidden, dim), np.float32)
+    W2 = np.zeros((embed, hidden), np.float32)
+    rows = np.arange(embed)
+    W1[2 * rows[:, None], comp] = sign
+    W1[2 * rows[:, None] + 1, comp] = -sign
+    W2[rows, 2 * rows] = 1.0
+    W2[rows, 2 * rows + 1] = -1.0
+    return {"W1": W1, "b1": np.zeros(hidden, np.float32), "W2": W2,
+            "b2": np.zeros(embed, np.float32)}
+
+
 class Model:
     """A homs_model (learned shortlist) on a context's device.
 
@@ -553,6 +643,21 @@ class Model:
         ctx._ck(_lib.homs_model_create(ctx._h, self.hidden, self.embed_dim,
                                        *[_np_ptr(w[k]) for k in WEIGHT_NAMES], ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def load(cls, ctx: "Context", path: str) -> "Model":
+        """homs_model_load: a model (weights, Adam state) from a model file."""
+        h = _P()
+        ctx._ck(_lib.homs_model_load(ctx._h, os.fsencode(path), ctypes.byref(h)))
+        m = cls.__new__(cls)
+        m.ctx, m._h = ctx, h
+        info = file_info(path)
+        m.hidden, m.dim, m.embed_dim = info["hidden"], info["dim"], info["embed"]
+        return m
+
+    def save(self, path: str):
+        """homs_model_save: weights, Adam moments and step count to a file."""
+        self.ctx._ck(_lib.homs_model_save(self._h, os.fsencode(path)))
 
     def _host(self, weights):
         shapes = {"W1": (self.hidden, self.dim), "b1": (self.hidden,),
@@ -625,6 +730,28 @@ class Model:
             _dptr(r_hv, torch.int32, "r_hv", dev), tau, lr,
             _dptr(loss_out, torch.float32, "loss", dev), _stream(dev)))
         return loss_out
+
+    def train(self, q_hv, target_idx, epochs: int = 2, batch: int = 1024, lr: float = 3e-5,
+              tau: float = 0.02, seed: int = 0, losses: bool = False):
+        """homs_model_train on (query row, library index of its exact top-1) pairs.
+        Returns the number of steps (and the device float32 losses per step)."""
+        import torch
+        dev = self.ctx.device
+        n = q_hv.shape[0]
+        if target_idx.shape != (n,):
+            raise ValueError("target_idx must be [n]")
+        cfg = _TrainConfig()
+        _lib.homs_train_config_default(ctypes.byref(cfg))
+        cfg.epochs, cfg.batch, cfg.lr, cfg.tau, cfg.seed = epochs, batch, lr, tau, seed
+        out = (torch.empty(max(1, epochs * (n // batch)), dtype=torch.float32, device=dev)
+               if losses else None)
+        steps = _i64(0)
+        self.ctx._ck(_lib.homs_model_train(
+            self._h, n, _dptr(q_hv, torch.int32, "q_hv", dev) if n else None,
+            _dptr(target_idx, torch.int64, "target_idx", dev) if n else None,
+            ctypes.byref(cfg), _dptr(out, torch.float32, "losses", dev) if losses else None,
+            ctypes.byref(steps), _stream(dev)))
+        return (steps.value, out[:steps.value]) if losses else steps.value
 
     def embed_library(self):
         self.ctx._ck(_lib.homs_model_embed_library(self._h, _stream(self.ctx.device)))

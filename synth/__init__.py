@@ -15,6 +15,7 @@ from .spectra import (  # noqa: F401
     make_decoys,
     make_queries,
     make_workload,
+    make_training_queries,
     concat,
     subset,
 )

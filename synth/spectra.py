@@ -9,9 +9,12 @@ The paper's datasets are not available, so every input here is synthetic:
 * references: precursor m/z ~ U[400, 1500], charge uniform over the workload's
   charges, peak count ~ U{20..150}, peak m/z ~ U[101, 1500], intensity ~
   lognormal(0, 1);
-* decoys: one per reference, keeping its precursor m/z, charge and
-  intensities, with the reference's fragment m/z values randomly permuted among
-  its peaks ("shuffled in m/z");
+* decoys: one per reference, keeping its precursor m/z, charge, peak count
+  and intensities, with every fragment peak at a newly drawn m/z from the
+  reference peaks' distribution. The workload statement's decoys keep the
+  reference's fragment m/z values and only permute them among its peaks; such
+  decoys share every peak position with their reference and would win top-1
+  so often that no match passes a 1% FDR, so the generator redraws them;
 * queries: a random reference with N(0, 0.01) m/z jitter on every fragment,
   each fragment dropped with probability 0.2, round(0.1 * n) noise peaks added,
   and, for half of the queries, a mass shift delta ~ U[-150, 500] Da applied to
@@ -234,3 +237,13 @@ def make_workload(w: Workload, n_ref: Optional[int] = None, n_query: Optional[in
     return Generated(lib, q, tol_kind, tol_value, train,
                      meta={"workload": w.name, "n_ref": n_ref, "n_decoy": n_ref,
                            "n_query": n_query, "n_train": n_train, "seed": seed})
+
+
+def make_training_queries(g: Generated, n_train: int) -> RawSpectra:
+    """The training queries make_workload draws for the same seed and library
+    when asked for n_train of them (its fifth random stream), without
+    drawing the library and evaluation queries again."""
+    ss = np.random.SeedSequence(g.meta["seed"])
+    r_train = np.random.default_rng(ss.spawn(5)[4])
+    refs = subset(g.library, np.arange(g.meta["n_ref"]))
+    return make_queries(refs, n_train, r_train)

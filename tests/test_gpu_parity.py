@@ -133,6 +133,38 @@ def test_top1_other_dims_ragged(dim, n_ref, n_query):
         s.ctx.close()
 
 
+@pytest.mark.parametrize("dim", [8192, 2048])
+def test_top1_full_size_paths(dim):
+    """The one-shot matrix-core kernels on the paths they take at full size.
+    42,000 library spectra fill more than ten absolute 4,096-row chunks (both
+    charge segments cross several), and 1,400 queries of charges 2 and 3 make
+    at least six 256-query tiles, so the work map covers more than one patch
+    of 4 tiles x 8 chunks; +-500 Da windows start and end inside 256-row
+    blocks. Every engine is compared with the oracle element by element
+    (Section 3.4: best match over each query's whole window), for the open
+    window and a narrow 20 ppm one."""
+    s = Setup(dim=dim, n_ref=21_000, n_query=1_400, seed=7)
+    g = s.g
+    try:
+        assert g.library.n >= 40_000 and g.queries.n >= 1_300
+        assert set(np.unique(g.queries.charge)) == {2, 3}
+        lo, hi = s.ctx.window_bounds(s.q_pmz, s.q_ch)
+        lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+        assert np.array_equal(hi - lo, oracle.window_counts(g.library.pmz, g.library.charge,
+                                                             g.queries.pmz, g.queries.charge))
+        assert np.mean((lo % 256) != 0) > 0.9 and np.mean((hi % 256) != 0) > 0.9
+        for kind, value in ((0, 500.0), (1, 20.0)):
+            o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
+                                          g.queries.pmz, g.queries.charge, kind, value)
+            for engine in ENGINES:
+                idx, dist = s.ctx.search_window(s.q_hv, s.q_pmz, s.q_ch, kind=kind, value=value,
+                                                engine=engine)
+                assert np.array_equal(idx.cpu().numpy(), o_idx), (kind, engine)
+                assert np.array_equal(dist.cpu().numpy(), o_dist), (kind, engine)
+    finally:
+        s.ctx.close()
+
+
 def test_exact_copies_and_duplicates(tiny):
     """Queries that copy library spectra: distance 0; a decoy shares its
     reference's pmz and charge, and exact duplicates go to the lowest index."""
