@@ -55,7 +55,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
 MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
-                    ("mfma_fp4", "cee04aab8d424ae0"): 2.6084e+11}
+                    ("mfma_fp4", "fb4f358d3740897a"): 2.6084e+11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
