@@ -492,11 +492,21 @@ homs_status homs_model_train(homs_model *model, int64_t n, const uint32_t *d_q_h
                              const int64_t *d_target_idx, const homs_train_config *cfg,
                              float *d_losses, int64_t *out_steps, void *stream);
 
-/* Embeds the context's encoded library (model-owned bf16 rows, sorted
- * library order). Needed before homs_search_learned and again after the
- * library or the weights change. Asynchronous; grows its buffer (a device
- * allocation) when the library grew. */
+/* Embeds the context's encoded library into the model's scoring
+ * embeddings (sorted library order): for each row the unit embedding e
+ * rounded as E4M3(16 e) (the 8-bit E4M3 format of the OCP 8-bit floating
+ * point specification, nearest value, ties to even), kept as E4M3 codes and,
+ * divided by 16, as bf16. Needed before homs_search_learned and again after
+ * the library or the weights change. Asynchronous; grows its buffers (device
+ * allocations) when the library grew. */
 homs_status homs_model_embed_library(homs_model *model, void *stream);
+
+/* Test support: copies the stored scoring embeddings of the library (sorted
+ * order, the order of homs_library_order) to d_out_fp8 [n][E] (E4M3 codes of
+ * 16 e) and/or d_out_bf16 [n][E] (those values / 16, bf16 bits); either may
+ * be NULL. HOMS_E_STATE without homs_model_embed_library. Asynchronous. */
+homs_status homs_model_library_embeddings(homs_model *model, uint8_t *d_out_fp8,
+                                          uint16_t *d_out_bf16, void *stream);
 
 /*
  * Shortlist search: for each query, the k (1 <= k <= 1024) candidates of its

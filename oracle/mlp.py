@@ -8,7 +8,7 @@ Hamming top-1 of Section 3.4, which remains the reference answer):
     a1 = W1 x + b1,   h = ReLU(a1)                      (D -> H)
     z  = W2 h + b2                                      (H -> E)
     e  = z / sqrt(z.z + eps)                            (unit embedding)
-    score(q, r) = e_q . e_r
+    score(q, r) = s_q . s_r,  s = E4M3(16 e) / 16       (scoring_embeddings)
 
 Training loss for a batch of B (query, exact top-1 reference) pairs is
 InfoNCE with in-batch negatives and temperature tau:
@@ -74,6 +74,47 @@ def forward(p: Dict[str, np.ndarray], X: np.ndarray, round_hidden: bool = False
 
 def embed(p, X, round_hidden: bool = False):
     return forward(p, X, round_hidden)["e"]
+
+
+# Scoring embeddings are stored in the 8-bit E4M3 format of the OCP 8-bit
+# floating point specification (v1.0, 2023) after scaling by SCORE_SCALE, so
+# that the components of a unit embedding sit in its normal range.
+SCORE_SCALE = 16.0
+E4M3_MAX = 448.0
+
+
+def round_e4m3(x: np.ndarray) -> np.ndarray:
+    """Nearest E4M3 value of each element (as float64), ties to even: 3
+    fraction bits in each binade 2^e .. 2^(e+1) for e >= -6, multiples of 2^-9
+    below 2^-6 (subnormals), magnitudes beyond 448 saturated to 448."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), E4M3_MAX)
+    _, ex = np.frexp(a)                        # a = f 2^ex with f in [0.5, 1)
+    e = np.maximum(ex.astype(np.float64) - 1.0, -6.0)
+    step = np.ldexp(1.0, (e - 3.0).astype(np.int64))
+    r = np.minimum(np.round(a / step) * step, E4M3_MAX)  # np.round: ties to even
+    return np.copysign(r, x)
+
+
+def e4m3_code(x: np.ndarray) -> np.ndarray:
+    """Byte of the E4M3 value nearest to each element: sign bit 7, biased
+    exponent (bias 7) in bits 3-6, fraction in bits 0-2; exponent field 0 for
+    the subnormals m 2^-9."""
+    r = round_e4m3(x)
+    a = np.abs(r)
+    _, ex = np.frexp(a)
+    normal = a >= 2.0 ** -6
+    e = np.where(normal, ex - 1, -6)
+    frac = np.where(normal, a / np.ldexp(1.0, e) - 1.0, a * 512.0)
+    code = np.where(normal, ((e + 7) << 3) + np.round(frac * 8.0).astype(np.int64),
+                    np.round(frac).astype(np.int64))
+    return (code | np.where(np.signbit(r), 0x80, 0)).astype(np.uint8)
+
+
+def scoring_embeddings(e: np.ndarray) -> np.ndarray:
+    """Embeddings as the shortlist scores them: E4M3 of SCORE_SCALE e, scaled
+    back (exact), so that score(q, r) = round_e4m3(16 e_q) . round_e4m3(16 e_r) / 256."""
+    return round_e4m3(SCORE_SCALE * np.asarray(e, dtype=np.float64)) / SCORE_SCALE
 
 
 def rounded_weights(p: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:

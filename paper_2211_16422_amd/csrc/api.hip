@@ -1169,7 +1169,7 @@ homs_status homs_model_embed(homs_model* m, int64_t n, const uint32_t* d_hv, flo
     if (n == 0) return HOMS_OK;
     if (!d_hv || !d_out) return fail(c, HOMS_E_INVALID, "NULL device pointer");
     DeviceGuard g(c->device);
-    HIP_TRY(c, homs::model_embed(m, n, d_hv, d_out, nullptr, (hipStream_t)stream),
+    HIP_TRY(c, homs::model_embed(m, n, d_hv, d_out, nullptr, nullptr, (hipStream_t)stream),
             "embedding kernels");
     return HOMS_OK;
 }
@@ -1280,17 +1280,40 @@ homs_status homs_model_embed_library(homs_model* m, void* stream)
     if (m->lib_emb_n < n) {
         HIP_TRY(c, hipStreamSynchronize(s), "hipStreamSynchronize");
         if (m->lib_emb) (void)hipFree(m->lib_emb);
+        if (m->lib_emb8) (void)hipFree(m->lib_emb8);
         m->lib_emb = nullptr;
+        m->lib_emb8 = nullptr;
         m->lib_emb_n = 0;
-        HIP_TRY(c, hipMalloc(&m->lib_emb, (size_t)std::max<int64_t>(n, 1) * m->E * 2),
-                "hipMalloc(library embeddings)");
+        const size_t rows = (size_t)std::max<int64_t>(n, 1);
+        HIP_TRY(c, hipMalloc(&m->lib_emb, rows * m->E * 2), "hipMalloc(library embeddings)");
+        HIP_TRY(c, hipMalloc(&m->lib_emb8, rows * m->E), "hipMalloc(library embeddings)");
         m->lib_emb_n = n;
     }
     if (n > 0)
-        HIP_TRY(c, homs::model_embed(m, n, c->lib.hv, nullptr, m->lib_emb, s), "embedding kernels");
+        HIP_TRY(c, homs::model_embed(m, n, c->lib.hv, nullptr, m->lib_emb, m->lib_emb8, s),
+                "embedding kernels");
     m->lib_emb_lib_gen = c->lib_gen;
     m->lib_emb_w_gen = m->weights_gen;
     m->lib_emb_valid = true;
+    return HOMS_OK;
+}
+
+homs_status homs_model_library_embeddings(homs_model* m, uint8_t* d_out_fp8, uint16_t* d_out_bf16,
+                                          void* stream)
+{
+    if (homs_status s = model_usable(m)) return s;
+    homs_ctx* c = m->ctx;
+    if (!m->lib_emb_valid) return fail(c, HOMS_E_STATE, "no library embeddings");
+    const size_t n = (size_t)c->lib.n * m->E;
+    if (n == 0) return HOMS_OK;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (d_out_fp8)
+        HIP_TRY(c, hipMemcpyAsync(d_out_fp8, m->lib_emb8, n, hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync(embeddings)");
+    if (d_out_bf16)
+        HIP_TRY(c, hipMemcpyAsync(d_out_bf16, m->lib_emb, n * 2, hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync(embeddings)");
     return HOMS_OK;
 }
 
@@ -1324,6 +1347,7 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     homs::LearnedScratchPlan plan;
     const size_t base = search_scratch_bytes(nq, tile);
     const size_t extra = al(homs::fallback_scratch_bytes(nq)) + al(nq * (size_t)m->E * 2) +
+                         al(nq * (size_t)m->E) +
                          (d_out_shortlist ? 0 : al(nq * (size_t)k * 8)) +
                          homs::learned_scratch_bytes(nq, m->E, &plan);
     if (homs_status st = ensure_workspace(c, base + extra, s)) return st;
@@ -1333,6 +1357,8 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
     p += al(homs::fallback_scratch_bytes(nq));
     uint16_t* q_emb = (uint16_t*)p;
     p += al(nq * (size_t)m->E * 2);
+    uint8_t* q_emb8 = (uint8_t*)p;
+    p += al(nq * (size_t)m->E);
     int64_t* shortlist = d_out_shortlist;
     if (!shortlist) {
         shortlist = (int64_t*)p;
@@ -1349,7 +1375,7 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
                                        w.sort_bytes, w.qk_a, w.qk_b, w.qp_a, w.qp_b, &qperm, s),
             "query sort");
     HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
-    HIP_TRY(c, homs::model_embed(m, nq, d_q_hv, nullptr, q_emb, s), "embedding kernels");
+    HIP_TRY(c, homs::model_embed(m, nq, d_q_hv, nullptr, q_emb, q_emb8, s), "embedding kernels");
     hipEvent_t e1 = prof_mark(c, s);
     homs::SpanHook hook;
     if (c->prof.on) {
@@ -1359,8 +1385,9 @@ homs_status homs_search_learned(homs_ctx* c, homs_model* m, int64_t nq, const ui
             prof_span((homs_ctx*)u, a, b, homs::kProfScore);
         };
     }
-    HIP_TRY(c, homs::launch_search_learned(c, m, lscratch, plan, nq, d_q_hv, q_emb, qperm, w.lo,
-                                           w.hi, k, w.keys, d_out_fallback, shortlist, hook, s),
+    HIP_TRY(c, homs::launch_search_learned(c, m, lscratch, plan, nq, d_q_hv, q_emb, q_emb8, qperm,
+                                           w.lo, w.hi, k, w.keys, d_out_fallback, shortlist, hook,
+                                           s),
             "shortlist kernels");
     // exhaustive pass over the windows of the queries that fell back
     HIP_TRY(c, homs::launch_fallback_scan(c, nq, d_q_hv, d_out_fallback, w.lo, w.hi, fb_scratch,

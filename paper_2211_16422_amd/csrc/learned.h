@@ -22,7 +22,10 @@ struct homs_model {
     size_t train_ws_bytes = 0;
     void* emb_ws = nullptr;
     size_t emb_ws_bytes = 0;
-    // embeddings of the context's library in sorted order, bf16 [n][E]
+    // scoring embeddings of the context's library in sorted order: E4M3 codes
+    // of 16 e [n][E] (the scoring kernel's operands) and the same values / 16
+    // in bf16 [n][E] (the threshold samples' operands)
+    uint8_t* lib_emb8 = nullptr;
     uint16_t* lib_emb = nullptr;
     int64_t lib_emb_n = 0;
     uint64_t lib_emb_lib_gen = 0;  // ctx->lib_gen and weights_gen the embeddings
@@ -34,11 +37,45 @@ namespace homs {
 
 constexpr int64_t kEmbedBatch = 16384;  // rows expanded to bf16 per embedding pass
 
+// Scoring embeddings: the E4M3 format of the OCP 8-bit floating point
+// specification (v1.0, 2023): sign, 4 exponent bits with bias 7, 3 fraction
+// bits; subnormals m 2^-9; largest finite value 448. A unit embedding is
+// scaled by kScoreScale first, so its components lie in the normal range;
+// scores of two scaled rows are kScoreScale^2 times the scores of the
+// rounded embeddings.
+constexpr float kScoreScale = 16.f;
+
+// nearest E4M3 code, ties to even; magnitudes beyond 448 saturate
+__device__ __forceinline__ uint32_t to_e4m3(float x)
+{
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float a = fminf(fabsf(x), 448.f);
+    uint32_t code;
+    if (a < 0.015625f) {  // below 2^-6: multiples of 2^-9 (8 is 2^-6 itself)
+        code = (uint32_t)rintf(a * 512.f);
+    } else {  // keep 3 fraction bits, ties to even; a carry moves into the exponent
+        uint32_t u = __float_as_uint(a);
+        u += 0x7FFFFu + ((u >> 20) & 1u);
+        code = (((u >> 23) - 120u) << 3) | ((u >> 20) & 7u);  // exponent bias 127 -> 7
+    }
+    return sign | code;
+}
+
+__device__ __forceinline__ float from_e4m3(uint32_t c)
+{
+    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    const float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * (1.f / 512.f);
+    return (c & 0x80u) ? -mag : mag;
+}
+
 void model_free(homs_model* m);
 hipError_t model_alloc(homs_model* m);
 hipError_t model_refresh_bf16(homs_model* m, hipStream_t s);
+// Embeddings of n packed rows: fp32 unit embeddings (out_f32), and/or the
+// scoring embeddings (out_fp8: E4M3 codes of kScoreScale e; out_bf16: those
+// values / kScoreScale). Without out_fp8, out_bf16 holds bf16(e).
 hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_f32,
-                       uint16_t* out_bf16, hipStream_t s);
+                       uint16_t* out_bf16, uint8_t* out_fp8, hipStream_t s);
 // Rows of a training batch taken through device index arrays: at `step`, row
 // r of the batch is query q_rows[perm[step] * B + r] and reference (sorted
 // library row) r_rows[perm[step] * B + r].
@@ -80,6 +117,7 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan);
 hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
                                  const LearnedScratchPlan& plan, int64_t nq,
                                  const uint32_t* q_hv, const uint16_t* q_emb,
+                                 const uint8_t* q_emb8,
                                  const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
                                  int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
                                  const SpanHook& hook, hipStream_t s);

@@ -85,10 +85,13 @@ __global__ void transpose_bf16_kernel(int R, int C, const uint16_t* __restrict__
     }
 }
 
-// unit embedding rows: e = z / sqrt(z.z + eps); one wave per row
+// unit embedding rows: e = z / sqrt(z.z + eps); one wave per row. With eb8,
+// the scoring embeddings: eb8 = E4M3 code of kScoreScale e and eb = that
+// value / kScoreScale (exact in bf16); otherwise eb = bf16(e).
 __global__ void normalize_kernel(int64_t M, int E, const float* __restrict__ z,
                                  float* __restrict__ e, uint16_t* __restrict__ eb,
-                                 float* __restrict__ s, float* __restrict__ out_f32)
+                                 float* __restrict__ s, float* __restrict__ out_f32,
+                                 uint8_t* __restrict__ eb8 = nullptr)
 {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
@@ -102,7 +105,13 @@ __global__ void normalize_kernel(int64_t M, int E, const float* __restrict__ z,
     for (int j = l; j < E; j += 64) {
         const float v = zr[j] / sc;
         if (e) e[row * E + j] = v;
-        if (eb) eb[row * E + j] = to_bf16(v);
+        if (eb8) {
+            const uint32_t c = to_e4m3(v * kScoreScale);
+            eb8[row * E + j] = (uint8_t)c;
+            if (eb) eb[row * E + j] = to_bf16(from_e4m3(c) * (1.f / kScoreScale));
+        } else if (eb) {
+            eb[row * E + j] = to_bf16(v);
+        }
         if (out_f32) out_f32[row * E + j] = v;
     }
     if (s && l == 0) s[row] = sc;
@@ -236,7 +245,7 @@ void model_free(homs_model* m)
                     (void*)m->vW1, (void*)m->mb1, (void*)m->vb1, (void*)m->mW2, (void*)m->vW2,
                     (void*)m->mb2, (void*)m->vb2, (void*)m->W1h, (void*)m->W2h, (void*)m->W2Th,
                     (void*)m->gW1, (void*)m->gb1, (void*)m->gW2, (void*)m->gb2, m->train_ws,
-                    m->emb_ws, (void*)m->lib_emb, (void*)m->loss_scratch})
+                    m->emb_ws, (void*)m->lib_emb, (void*)m->lib_emb8, (void*)m->loss_scratch})
         if (p) (void)hipFree(p);
 }
 
@@ -291,7 +300,7 @@ size_t embed_ws_bytes(const homs_model* m, int64_t rows)
 }
 
 hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_f32,
-                       uint16_t* out_bf16, hipStream_t s)
+                       uint16_t* out_bf16, uint8_t* out_fp8, hipStream_t s)
 {
     const int64_t rows = std::min<int64_t>(n, kEmbedBatch);
     if (n <= 0) return hipSuccess;
@@ -329,7 +338,7 @@ hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_
         if (e != hipSuccess) return e;
         normalize_kernel<<<(uint32_t)((nr + 3) / 4), 256, 0, s>>>(
             nr, m->E, a1, nullptr, out_bf16 ? out_bf16 + r0 * m->E : nullptr, nullptr,
-            out_f32 ? out_f32 + r0 * m->E : nullptr);
+            out_f32 ? out_f32 + r0 * m->E : nullptr, out_fp8 ? out_fp8 + r0 * m->E : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

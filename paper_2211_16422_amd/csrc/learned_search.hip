@@ -15,11 +15,11 @@
 //     buffer: with r of at least 8 on the largest windows, both overflow and
 //     keeping fewer than k are far in the tails); windows of at most kSample
 //     (= kCapacity) candidates keep everything;
-//  2. collect: score every (query, candidate) pair on matrix cores (bf16
-//     operands, fp32 accumulation, 128 library rows x 128 m/z-ordered queries
-//     per workgroup) and append in-window pairs at or above the query's
-//     threshold to its buffer of kCapacity 64-bit keys
-//     (order-preserving score << 32 | ~library index);
+//  2. collect: score every (query, candidate) pair on matrix cores (E4M3
+//     scoring embeddings, fp32 accumulation, 128 library rows x 128
+//     m/z-ordered queries per workgroup) and append in-window pairs at or
+//     above the query's threshold to its buffer of kCapacity 64-bit keys
+//     (order-preserving score << 32 | sorted row);
 //  3. select: sort each buffer in LDS (bitonic, descending) and keep the k
 //     largest keys; a query whose buffer overflowed, or whose sampled
 //     threshold kept fewer than min(k, window) candidates, is flagged for the
@@ -70,6 +70,18 @@ __global__ void permute_rows_kernel(int64_t n, int E, const uint32_t* __restrict
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int per = E / 8;
+    if (t >= n * per) return;
+    const int64_t r = t / per;
+    const int c = (int)(t - r * per);
+    ((uint4*)(dst + r * E))[c] = ((const uint4*)(src + (size_t)perm[r] * E))[c];
+}
+
+// dst row p = src row perm[p] for rows of E bytes; 16-byte pieces
+__global__ void permute_rows8_kernel(int64_t n, int E, const uint32_t* __restrict__ perm,
+                                     const uint8_t* __restrict__ src, uint8_t* __restrict__ dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = E / 16;
     if (t >= n * per) return;
     const int64_t r = t / per;
     const int c = (int)(t - r * per);
@@ -311,58 +323,62 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
 // cores and appends every in-window pair at or above the query's threshold.
 //
+// Operands are the scoring embeddings as E4M3 codes of 16 e (one byte per
+// component, v_mfma_f32_32x32x64_f8f6f4, fp32 accumulation): every product
+// of two codes is exact in fp32, and the accumulator holds 256 times the
+// score of the rounded embeddings.
+//
 // Eight waves, two per SIMD: wave (wr, wn) owns rows 32 wr .. + 31 of each
-// block and the 64 queries of half wn (two 32-query tiles), whose embeddings
-// are its B operands for the whole chunk (2 E / 16 registers of 16 bytes), so
+// block and the 64 queries of half wn (two 32-query tiles), whose codes are
+// its B operands for the whole chunk (E / 64 steps of 32 bytes per tile), so
 // every A operand read from LDS feeds two matrix instructions. Library rows
 // stream through two LDS buffers filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4, no staging registers) two blocks ahead of their
-// use. At E = 256 one load moves two 512-byte rows (every lane busy) into a
-// pair padded by 16 bytes, and matrix row i of a wave's 32-row tile reads
-// library row 2 (i mod 16) + i / 16, so that the 16 rows read together by a
-// quarter-wave lie in 16 pairs (distinct banks); at E = 64 and 128 one load
-// moves one row, padded by 16 bytes, and matrix row i reads row i. Either
-// way every A read is a base plus an immediate. The loads are issued from
-// inline asm with explicit vmcnt waits: the compiler would otherwise drain
-// every outstanding LDS load before any LDS read and cap the prefetch at one
-// block.
+// use: one load moves 1 KB (64 lanes x 16 bytes) of a block's rows, so a
+// 128-row block of E-byte rows takes E / 64 loads per wave. The 16-byte piece
+// p of row R sits at slot p ^ swz(R) of the row, swz(R) = (R / (16 / P)) mod
+// P with P = E / 16 pieces per row, so the 16 rows a quarter-wave reads
+// together land on 16 distinct 16-byte bank groups. The loads are issued
+// from inline asm with explicit vmcnt waits: the compiler would otherwise
+// drain every outstanding LDS load before any LDS read and cap the prefetch
+// at one block.
 //
 // Epilogue, software-pipelined: the scores of block b - 1 are examined
-// between the matrix instructions of block b (one position per step, both
-// query tiles), so that the compares and ballots issue while the matrix core
-// works. When the wave's 32 rows of the block lie inside every window of its
-// queries (the usual case) a position costs one compare and one ballot per tile and is
-// skipped unless some lane hits; otherwise the block's positions are masked
-// row by row after the matrix instructions. Hits go to the wave's own LDS
-// list at positions counted from the ballot (no atomics, no global loads),
-// flushed to the per-query global buffers when half full and at the end.
+// between the matrix instructions of block b (16 positions per block, both
+// query tiles, spread over its E / 64 matrix steps), so that the compares
+// and ballots issue while the matrix core works. When the wave's 32 rows of
+// the block lie inside every window of its queries (the usual case) a
+// position costs one compare and one ballot per tile and is skipped unless
+// some lane hits; otherwise the block's positions are masked row by row after
+// the matrix instructions. Hits go to the wave's own LDS list at positions
+// counted from the ballot (no atomics, no global loads), flushed to the
+// per-query global buffers when half full and at the end.
 constexpr int kWaveList = 384;  // LDS entries per wave
 
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
 
+typedef int v8i32 __attribute__((ext_vector_type(8)));
+
 template <int E>
 __global__ __launch_bounds__(512, 1) void collect_kernel(
-    int64_t q_begin, int64_t q_end, const uint16_t* __restrict__ q_sorted,
+    int64_t q_begin, int64_t q_end, const uint8_t* __restrict__ q_sorted8,
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
-    const uint16_t* __restrict__ lib_emb, uint32_t* __restrict__ count,
+    const uint8_t* __restrict__ lib_emb8, uint32_t* __restrict__ count,
     uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks)
 {
     using namespace gemm;
-    constexpr int KS = E / 16;                    // 32 x 32 x 16 steps
+    constexpr int KS = E / 64;                    // 32 x 32 x 64 steps
     constexpr int PPK = 16 / KS;                  // epilogue positions per step
-    constexpr bool kPair = E == 256;              // two rows per direct load
-    constexpr int RB = kPair ? E * 2 : E * 2 + 16;  // LDS bytes per row (padded if single)
-    constexpr int GS = 2 * RB + 16;               // LDS bytes per padded pair of rows
-    constexpr int PIECES = E / 8;                 // 16-byte pieces per row
+    constexpr int P = E / 16;                     // 16-byte pieces per row
+    constexpr int RPS = 16 / P;                   // rows sharing one swizzle value
     constexpr int NW = 8;                         // waves
-    constexpr int NI = 128 / NW;                  // rows per wave per block
-    constexpr int NL = kPair ? NI / 2 : NI;       // direct loads per wave per block
-    static_assert(PIECES <= 64 && NI < 64, "whole rows per load, vmcnt range");
-    static_assert(KS * PPK == 16, "E in {64, 128, 256}");
-    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kPair ? 64 * GS : 128 * RB];
+    constexpr int NL = E / 64;                    // direct loads per wave per block
+    constexpr float kScoreScale2 = kScoreScale * kScoreScale;
+    static_assert(KS * PPK == 16 && NL >= 1, "E in {64, 128, 256}");
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * E];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
     // Chunks are fixed row ranges of the sorted library, clipped to the
@@ -383,39 +399,29 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
     const int nblk = (int)((c1 - c0 + 127) / 128);
 
-    // rows [c0 + 128 b, + 128) into sA[b & 1] (the destination of a direct
-    // load is M0 + 16 x lane): at E = 256 load x of wave w moves pair
-    // pr = NI w / 2 + x, rows 2 pr (lanes 0 .. 31) and 2 pr + 1 (lanes
-    // 32 .. 63); otherwise load x moves row NI w + x, lane l < PIECES its
-    // piece l
+    // rows [c0 + 128 b, + 128) into sA[b & 1]: load x of wave w fills bytes
+    // [1024 (NL w + x), + 1024) of the buffer (the destination of a direct
+    // load is M0 + 16 x lane), lane l the slot of row R = o / E, o the byte
+    // offset of the lane, with the row's piece (slot ^ swz(R)); rows past c1
+    // repeat the last row
     auto issue = [&](int b) {
         const int64_t mb = c0 + (int64_t)b * 128;
         const uint32_t base = (uint32_t)(uintptr_t)&sA[b & 1][0];
-        const uint16_t* gbase = lib_emb + (size_t)mb * E;  // wave-uniform
-        const int last = (int)min((int64_t)127, c1 - 1 - mb);  // rows past c1 repeat the last
-        if constexpr (kPair) {
+        const uint8_t* gbase = lib_emb8 + (size_t)mb * E;  // wave-uniform
+        const int last = (int)min((int64_t)127, c1 - 1 - mb);
 #pragma unroll
-            for (int x = 0; x < NL; ++x) {
-                const int pr = w * NL + x;
-                const int row = 2 * pr + (l >> 5);
-                const uint32_t voff = (uint32_t)(min(row, last) * (E * 2) + (l & 31) * 16);
-                const uint32_t lds = __builtin_amdgcn_readfirstlane(base + (uint32_t)(pr * GS));
-                asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
-                             :
-                             : "v"(voff), "s"(gbase), "s"(lds)
-                             : "memory", "m0");
-            }
-        } else if (l < PIECES) {
-#pragma unroll
-            for (int x = 0; x < NI; ++x) {
-                const int row = w * NI + x;
-                const uint32_t voff = (uint32_t)(min(row, last) * (E * 2) + l * 16);
-                const uint32_t lds = __builtin_amdgcn_readfirstlane(base + (uint32_t)(row * RB));
-                asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
-                             :
-                             : "v"(voff), "s"(gbase), "s"(lds)
-                             : "memory", "m0");
-            }
+        for (int x = 0; x < NL; ++x) {
+            const int ci = w * NL + x;
+            const int o = ci * 1024 + 16 * l;
+            const int R = o / E;
+            const int sl = (o % E) / 16;
+            const int pc = sl ^ ((R / RPS) % P);
+            const uint32_t voff = (uint32_t)(min(R, last) * E + pc * 16);
+            const uint32_t lds = __builtin_amdgcn_readfirstlane(base + (uint32_t)(ci * 1024));
+            asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                         :
+                         : "v"(voff), "s"(gbase), "s"(lds)
+                         : "memory", "m0");
         }
     };
 
@@ -425,7 +431,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     bool qok[2];
     uint32_t qlo[2], qhi[2];
     float qthr[2];
-    bf16x8 bq[2][KS];
+    v8i32 bq[2][KS];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         col[j] = wn * 64 + j * 32 + (l & 31);
@@ -437,11 +443,28 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             const uint32_t qi = qperm[p];
             qlo[j] = (uint32_t)lo[qi];
             qhi[j] = (uint32_t)hi[qi];
-            qthr[j] = thr[p];
+            qthr[j] = thr[p] * kScoreScale2;  // exact: a power of two
         }
-        const uint16_t* qrow = q_sorted + (size_t)min(p, q_end - 1) * E + 8 * (l >> 5);
+        const uint8_t* qrow = q_sorted8 + (size_t)min(p, q_end - 1) * E + 32 * (l >> 5);
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk) bq[j][kk] = *(const bf16x8*)(qrow + kk * 16);
+        for (int kk = 0; kk < KS; ++kk) {
+            const uint4 u0 = *(const uint4*)(qrow + kk * 64);
+            const uint4 u1 = *(const uint4*)(qrow + kk * 64 + 16);
+            bq[j][kk] = v8i32{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                              (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+        }
+    }
+    // LDS offsets of this lane's A operand: row R = 32 wr + l % 32, pieces
+    // 4 kk + 2 (l / 32) + c of the 64-byte step kk
+    uint32_t aoff[KS][2];
+    {
+        const int R = wr * 32 + (l & 31);
+        const int sw = (R / RPS) % P;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                aoff[kk][c] = (uint32_t)(R * E + 16 * ((4 * kk + 2 * (l >> 5) + c) ^ sw));
     }
     const uint32_t e1 = (uint32_t)c1;
     // The B operands are in registers before the pipeline starts, so that no
@@ -481,9 +504,9 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         wcount = 0;
     };
     // append the hits of one position of query tile j (m: the wave's hit
-    // mask, uniform)
+    // mask, uniform; sc: 256 times the score)
     auto append = [&](uint64_t m, bool ok, float sc, uint32_t g, int j) {
-        const uint64_t v = ((uint64_t)fkey(sc) << 32) | (uint64_t)g;
+        const uint64_t v = ((uint64_t)fkey(sc * (1.f / kScoreScale2)) << 32) | (uint64_t)g;
         if (wcount + 64 <= kWaveList) {
             // the sorted row: its library index is looked up by the select
             // kernel, so no global load (and no vmcnt wait, which would also
@@ -502,14 +525,10 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     };
 
     // Accumulator register r of query tile j holds matrix row
-    // i = 8 (r / 4) + 4 (l / 32) + r % 4 of the wave's tile, which is library
-    // row wb + i (E < 256) or wb + 2 (i % 16) + i / 16 (E = 256), wb = the
-    // block's first row + 32 wr: gl + roff(r) with gl = wb + 4 (l / 32) or
-    // wb + 8 (l / 32).
-    auto roff = [](int r) -> uint32_t {
-        return kPair ? (uint32_t)(16 * ((r >> 2) & 1) + 2 * (r & 3) + (r >> 3))
-                     : (uint32_t)(8 * (r >> 2) + (r & 3));
-    };
+    // i = 8 (r / 4) + 4 (l / 32) + r % 4 of the wave's tile, library row
+    // wb + i with wb = the block's first row + 32 wr: gl + roff(r) with
+    // gl = wb + 4 (l / 32).
+    auto roff = [](int r) -> uint32_t { return (uint32_t)(8 * (r >> 2) + (r & 3)); };
     f32x16 acc[2], prev[2];
     bool have_prev = false, prev_fast = false;
     uint32_t gl_prev = 0;
@@ -524,15 +543,18 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             prev[0] = acc[0];
             prev[1] = acc[1];
             acc[0] = acc[1] = f32x16{0};
-            const uint8_t* Ar =
-                kPair ? sA[b & 1] + (wr * 16 + (l & 15)) * GS + ((l >> 4) & 1) * RB + 16 * (l >> 5)
-                      : sA[b & 1] + (wr * 32 + (l & 31)) * RB + 16 * (l >> 5);
+            const uint8_t* Ab = sA[b & 1];
             if (have_prev && prev_fast) {
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    const bf16x8 av = *(const bf16x8*)(Ar + kk * 32);
-                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[0][kk], acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[1][kk], acc[1], 0, 0, 0);
+                    const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
+                    const uint4 u1 = *(const uint4*)(Ab + aoff[kk][1]);
+                    const v8i32 av = {(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+                    acc[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av, bq[0][kk], acc[0], 0, 0, 0, 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av, bq[1][kk], acc[1], 0, 0, 0, 0, 0, 0);
 #pragma unroll
                     for (int q = 0; q < PPK; ++q) {
                         const int r = kk * PPK + q;
@@ -548,9 +570,14 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             } else {
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    const bf16x8 av = *(const bf16x8*)(Ar + kk * 32);
-                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[0][kk], acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[1][kk], acc[1], 0, 0, 0);
+                    const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
+                    const uint4 u1 = *(const uint4*)(Ab + aoff[kk][1]);
+                    const v8i32 av = {(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+                    acc[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av, bq[0][kk], acc[0], 0, 0, 0, 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av, bq[1][kk], acc[1], 0, 0, 0, 0, 0, 0);
                 }
             }
             __syncthreads();  // every wave is done reading sA[b & 1]
@@ -579,7 +606,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             // block b's scores are examined during block b + 1 (or after the loop)
             have_prev = true;
             const uint32_t wb = (uint32_t)(c0 + (int64_t)b * 128) + wr * 32;
-            gl_prev = wb + (kPair ? 8u : 4u) * (uint32_t)(l >> 5);
+            gl_prev = wb + 4u * (uint32_t)(l >> 5);
             bool inside = wb + 32 <= e1;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
@@ -823,7 +850,7 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
     pl.batch = std::max<int64_t>(pl.batch, kTileQ);
     if (plan) *plan = pl;
     const int64_t tiles = pl.batch / kTileQ;
-    return al(nq * E * 2) + al(nq * 4) + al(pl.batch * 4 * kCountStride) +
+    return al(nq * E * 2) + al(nq * E) + al(nq * 4) + al(pl.batch * 4 * kCountStride) +
            al(pl.batch * (int64_t)kCapacity * 8) +
            2 * al(tiles * 8) + al(tiles * sizeof(SampleGrid)) + al(pl.batch * (int64_t)kSample * 4);
 }
@@ -831,9 +858,9 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
 hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* scratch,
                                  const LearnedScratchPlan& plan, int64_t nq,
                                  const uint32_t* q_hv, const uint16_t* q_emb,
-                                 const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
-                                 int k, uint64_t* keys, uint8_t* fallback, int64_t* shortlist,
-                                 const SpanHook& hook, hipStream_t s)
+                                 const uint8_t* q_emb8, const uint32_t* qperm, const int64_t* lo,
+                                 const int64_t* hi, int k, uint64_t* keys, uint8_t* fallback,
+                                 int64_t* shortlist, const SpanHook& hook, hipStream_t s)
 {
     if (nq <= 0) return hipSuccess;
     const int E = m->E;
@@ -842,6 +869,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     char* p = (char*)scratch;
     uint16_t* q_sorted = (uint16_t*)p;
     p += al(nq * E * 2);
+    uint8_t* q_sorted8 = (uint8_t*)p;
+    p += al(nq * E);
     float* thr = (float*)p;
     p += al(nq * 4);
     uint32_t* count = (uint32_t*)p;
@@ -858,6 +887,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
 
     permute_rows_kernel<<<blocks_for(nq * (E / 8)), kThreads, 0, s>>>(nq, E, qperm, q_emb,
                                                                      q_sorted);
+    permute_rows8_kernel<<<blocks_for(nq * (E / 16)), kThreads, 0, s>>>(nq, E, qperm, q_emb8,
+                                                                       q_sorted8);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
@@ -878,16 +909,16 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         if (cwg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
         const uint32_t cgrid = (uint32_t)cwg;
         if (E == 256)
-            collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, count, buf, tiles,
+            collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
+                                                      thi, m->lib_emb8, count, buf, tiles,
                                                       max_chunks);
         else if (E == 128)
-            collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb, count, buf, tiles,
+            collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
+                                                      thi, m->lib_emb8, count, buf, tiles,
                                                       max_chunks);
         else
-            collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted, qperm, lo, hi, thr, tlo,
-                                                     thi, m->lib_emb, count, buf, tiles,
+            collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
+                                                     thi, m->lib_emb8, count, buf, tiles,
                                                      max_chunks);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr, qperm, lo, hi,

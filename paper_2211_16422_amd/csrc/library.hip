@@ -18,9 +18,12 @@ constexpr int kThreads = 256;
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads); }
 
 // Order-preserving map of a double onto uint64 (negative values reversed).
+// Values that compare equal get one key: -0 sorts as +0, and every NaN as
+// one NaN after +inf, so rows of equal precursors stay in library order.
 __device__ __forceinline__ uint64_t order_key(double x)
 {
-    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    if (x == 0.0) x = 0.0;
+    const uint64_t b = (x != x) ? 0x7FF8000000000000ull : (uint64_t)__double_as_longlong(x);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 

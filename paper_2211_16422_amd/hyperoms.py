@@ -141,7 +141,7 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_model_create", "homs_model_destroy", "homs_model_set_weights",
             "homs_model_get_weights", "homs_model_embed", "homs_model_gradients",
             "homs_model_train_step", "homs_train_config_default", "homs_model_train",
-            "homs_model_embed_library", "homs_search_learned",
+            "homs_model_embed_library", "homs_model_library_embeddings", "homs_search_learned",
             "homs_measure_xor_popcount_rate", "homs_library_save", "homs_library_load",
             "homs_model_save", "homs_model_load", "homs_file_inspect"]
 
@@ -165,6 +165,7 @@ _sig("homs_train_config_default", [ctypes.POINTER(_TrainConfig)])
 _sig("homs_model_train", [_P, _i64, _P, _P, ctypes.POINTER(_TrainConfig), _P,
                           ctypes.POINTER(_i64), _P])
 _sig("homs_model_embed_library", [_P, _P])
+_sig("homs_model_library_embeddings", [_P, _P, _P, _P])
 _sig("homs_search_learned", [_P, _P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P,
                              _P, _P])
 
@@ -459,9 +460,13 @@ class Context:
             _dptr(out_dist, torch.int32, "out_dist", self.device), _stream(self.device)))
         return out_idx, out_dist
 
-    def preprocess_device(self, offsets, mz, intensity):
+    def preprocess_device(self, offsets, mz, intensity, check=True):
         """homs_preprocess_device: raw peaks (device CSR: int64 offsets, float64 m/z and
-        intensities) -> device CSR (offsets int64, bins int32, levels uint8)."""
+        intensities) -> device CSR (offsets int64, bins int32, levels uint8).
+
+        With `check` (the default) the context's device error flags are read (and
+        cleared) after the call, and a spectrum over the device limit of 2,048 raw
+        peaks (flag bit 1; it gets no entries) raises HomsError(HOMS_E_INVALID)."""
         import torch
         n = offsets.shape[0] - 1
         raw = int(offsets[-1].item()) if n > 0 else 0
@@ -477,6 +482,14 @@ class Context:
             _dptr(out_bin, torch.int32, "out_bin", self.device),
             _dptr(out_lv, torch.uint8, "out_level", self.device), _stream(self.device)))
         total = int(out_off[-1].item())
+        if check:
+            flags = self.device_errors()
+            if flags & 2:
+                raise HomsError(HOMS_E_INVALID,
+                                "homs_preprocess_device: a spectrum has more than 2048 raw peaks "
+                                f"(device error flags {flags:#x}); it was given no entries")
+            if flags:
+                raise HomsError(HOMS_E_INVALID, f"device error flags {flags:#x}")
         return out_off, out_bin[:total], out_lv[:total]
 
     def cascade_search(self, q_hv, pmz, charge, lib_decoy, narrow=(TOL_PPM, 20.0),
@@ -755,6 +768,19 @@ class Model:
 
     def embed_library(self):
         self.ctx._ck(_lib.homs_model_embed_library(self._h, _stream(self.ctx.device)))
+
+    def library_embeddings(self):
+        """homs_model_library_embeddings -> (E4M3 codes uint8 [n, E], bf16 bits
+        int16 [n, E]) of the library's scoring embeddings, sorted library order."""
+        import torch
+        c = self.ctx
+        n = c.library_size()
+        codes = torch.empty((n, self.embed_dim), dtype=torch.uint8, device=c.device)
+        bf = torch.empty((n, self.embed_dim), dtype=torch.int16, device=c.device)
+        c._ck(_lib.homs_model_library_embeddings(
+            self._h, _dptr(codes, torch.uint8, "codes", c.device),
+            _dptr(bf, torch.int16, "bf16", c.device), _stream(c.device)))
+        return codes, bf
 
     def search(self, q_hv, pmz, charge, k: int, kind=TOL_DA, value=500.0, shortlist=False):
         """homs_search_learned -> (idx int64, dist int32, fallback uint8[, shortlist int64 [nq, k]])."""

@@ -11,9 +11,15 @@ flips of the hidden layer. Tolerances:
   embeddings   |e_gpu - e_oracle| <= 1e-3 per element, row norm <= 5e-3
                (against the unrounded float64 oracle: row norm <= 3e-2)
   gradients    ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-2 per parameter
-  scores       members of a shortlist score at least the oracle's k-th score
-               minus 1e-2 and non-members at most that score plus 1e-2
-               (two unit embeddings each within 5e-3 of the oracle's)
+  scores       the shortlist scores the E4M3 scoring embeddings,
+               round_e4m3(16 e) / 16 (mlp.scoring_embeddings); members of a
+               shortlist score at least the oracle's k-th score minus 1e-2
+               and non-members at most that score plus 1e-2 (two unit
+               embeddings each within 5e-3 of the oracle's, and E4M3
+               rounding flips where the two sit near a rounding midpoint:
+               one step of 2^-4 of a component each, random in sign)
+  E4M3 codes   exact: the stored codes are the nearest E4M3 values of 16 e
+               of the GPU's own fp32 embeddings
   rescoring    exact: (distance, index) = the lexicographic minimum over the
                returned shortlist of the oracle's Hamming distances.
 """
@@ -61,8 +67,9 @@ def _rand_hv(n, D, seed):
 
 
 def _oracle_embed(p32, hv, D, round_out=False):
+    """The oracle's embeddings; with round_out, the scoring embeddings."""
     e = mlp.embed(mlp.rounded_weights(_f64(p32)), mlp.bipolar(hv, D), round_hidden=True)
-    return mlp.round_bf16(e) if round_out else e
+    return mlp.scoring_embeddings(e) if round_out else e
 
 
 @pytest.mark.parametrize("D,H,E,n", [(2048, 256, 64, 333), (8192, 1024, 256, 200)])
@@ -154,6 +161,38 @@ def test_training_lowers_the_loss():
     assert losses[-1] < 0.5 * first, (first, losses[-1])
     m.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("D,H,E", [(2048, 256, 64), (8192, 1024, 256)])
+def test_scoring_embeddings_are_e4m3(D, H, E):
+    """The library's stored scoring embeddings are, element for element, the
+    E4M3 code nearest to 16 times the GPU's own fp32 embedding of that row
+    (ties to even; oracle mlp.e4m3_code), and their bf16 copies hold exactly
+    those values divided by 16."""
+    import torch
+    h = _h()
+    g = make_workload(WORKLOADS["tiny"], n_ref=700, n_query=1, seed=31)
+    with h.Context(h.Params(dim=D)) as ctx:
+        lib = g.library
+        lo, lb, ll = h.preprocess(ctx.params, lib.offsets, lib.mz, lib.intensity)
+        ctx.encode_library(*h.to_device_csr(lo, lb, ll, "cuda:0"), _dev(lib.pmz),
+                           _dev(lib.charge))
+        m = h.Model(ctx, _weights(D, H, E, seed=E))
+        m.embed_library()
+        codes, bf = m.library_embeddings()
+        order = ctx.library_order().to(torch.int64)
+        e = m.embed(ctx.library_export()[order].contiguous())
+        torch.cuda.synchronize()
+        e = e.cpu().numpy().astype(np.float64)
+        codes = codes.cpu().numpy()
+        want = mlp.e4m3_code(16.0 * e)
+        assert np.array_equal(codes, want), int(np.sum(codes != want))
+        vals = bf.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+        vals = vals.view(np.float32).astype(np.float64)
+        assert np.array_equal(vals, mlp.round_e4m3(16.0 * e) / 16.0)
+        # the codes span the format: normal values of several binades and zeros
+        assert len(np.unique(codes)) > 60
+        m.close()
 
 
 class LearnedSetup:
@@ -429,38 +468,43 @@ def test_model_train_equals_its_steps():
 
 
 def test_training_raises_agreement():
-    """Top-1 agreement with the exhaustive search (Section 3.4) of the k = 8
-    shortlist on held-out queries, for three networks of the same shape: the
-    random initial weights, a training-free signed block-sum sketch of the
-    hypervector (sketch_weights) and the initial weights after
-    homs_model_train on (training query, exact top-1) pairs. The criterion,
-    fixed before the run that introduced the sketch: training must remove at
-    least a fifth of the misses of each of the other two."""
+    """Top-1 agreement with the exhaustive search (Section 3.4) of k = 4 and
+    k = 8 shortlists on 1,000 held-out queries, for three networks of the same
+    shape: the random initial weights, a training-free signed block-sum sketch
+    of the hypervector (sketch_weights), and the initial weights after
+    homs_model_train on 16,384 (training query, exact top-1) pairs. Criterion:
+    at both k, training removes at least a fifth of the misses of each of the
+    other two. The training settings (6 epochs of batches of 256, learning
+    rate 1e-4, tau 0.05) were chosen on another workload seed; this seed is
+    held out."""
     h = _h()
-    s = LearnedSetup(n_query=400, seed=6, n_train=4096)
+    s = LearnedSetup(n_query=1000, seed=16, n_train=16384)
     try:
         g = s.g
         o_idx, _ = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
                                  g.queries.pmz, g.queries.charge, 0, 500.0)
-        k = 8
         has = o_idx >= 0
+        ks = (4, 8)
 
         def agreement():
             s.model.embed_library()
-            idx, _, fb = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k)
-            return float(np.mean(idx.cpu().numpy()[has] == o_idx[has]))
+            out = []
+            for k in ks:
+                idx, _, fb = s.model.search(s.q_hv, s.q_pmz, s.q_ch, k)
+                out.append(float(np.mean(idx.cpu().numpy()[has] == o_idx[has])))
+            return np.array(out)
 
         untrained = agreement()
         s.model.set_weights(h.sketch_weights(s.D, 256, 64, seed=77))
         sketch = agreement()
         s.model.set_weights(s.p)
         t_hv, t_idx = _training_pairs(s)
-        steps = s.model.train(t_hv, t_idx, epochs=6, batch=256, lr=1e-3, tau=0.05, seed=0)
-        assert steps >= 6 * 15
+        steps = s.model.train(t_hv, t_idx, epochs=6, batch=256, lr=1e-4, tau=0.05, seed=0)
+        assert steps >= 6 * 60
         trained = agreement()
-        print(f"top-1 agreement at k={k}: untrained {untrained:.3f}, training-free sketch "
-              f"{sketch:.3f}, trained {trained:.3f}")
-        assert 1.0 - trained < 0.8 * (1.0 - untrained), (untrained, trained)
-        assert 1.0 - trained < 0.8 * (1.0 - sketch), (sketch, trained)
+        print(f"top-1 agreement at k={ks}: untrained {untrained}, training-free sketch "
+              f"{sketch}, trained {trained}")
+        assert np.all(1.0 - trained < 0.8 * (1.0 - untrained)), (untrained, trained)
+        assert np.all(1.0 - trained < 0.8 * (1.0 - sketch)), (sketch, trained)
     finally:
         s.close()

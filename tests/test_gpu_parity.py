@@ -152,7 +152,15 @@ def test_top1_full_size_paths(dim):
         lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
         assert np.array_equal(hi - lo, oracle.window_counts(g.library.pmz, g.library.charge,
                                                              g.queries.pmz, g.queries.charge))
-        assert np.mean((lo % 256) != 0) > 0.9 and np.mean((hi % 256) != 0) > 0.9
+        # window edges fall inside 256-row blocks, except where a window is
+        # clipped at its charge segment's first or last row (queries within
+        # 500 Da of the precursor range's ends: 41% of the lower edges and 51%
+        # of the upper ones with this seed)
+        n2 = int(np.sum(g.library.charge == 2))
+        starts, ends = np.array([0, n2]), np.array([n2, g.library.n])
+        free_lo, free_hi = ~np.isin(lo, starts), ~np.isin(hi, ends)
+        assert free_lo.mean() > 0.4 and free_hi.mean() > 0.4
+        assert np.mean(lo[free_lo] % 256 != 0) > 0.95 and np.mean(hi[free_hi] % 256 != 0) > 0.95
         for kind, value in ((0, 500.0), (1, 20.0)):
             o_idx, o_dist = oracle.search(s.op, s.o_lib, g.library.pmz, g.library.charge, s.o_q,
                                           g.queries.pmz, g.queries.charge, kind, value)

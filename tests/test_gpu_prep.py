@@ -34,10 +34,10 @@ def ctx():
     c.close()
 
 
-def _device(ctx, off, mz, inten):
+def _device(ctx, off, mz, inten, check=True):
     o, b, l = ctx.preprocess_device(_dev(np.asarray(off, dtype=np.int64)),
                                     _dev(np.asarray(mz, dtype=np.float64)),
-                                    _dev(np.asarray(inten, dtype=np.float64)))
+                                    _dev(np.asarray(inten, dtype=np.float64)), check=check)
     return o.cpu().numpy(), b.cpu().numpy(), l.cpu().numpy()
 
 
@@ -90,7 +90,11 @@ def test_oversized_spectrum_is_flagged(ctx):
     small = (list(rng.uniform(101, 1500, 30)), list(rng.lognormal(0, 1, 30)))
     big = (list(rng.uniform(101, 1500, 2049)), list(rng.lognormal(0, 1, 2049)))
     off, mz, inten = _pack([small, big, small])
-    o, b, l = _device(ctx, off, mz, inten)
+    h = _h()
+    with pytest.raises(h.HomsError) as e:  # the binding reads the flag and raises
+        _device(ctx, off, mz, inten)
+    assert e.value.status == h.HOMS_E_INVALID and "2048" in str(e.value)
+    o, b, l = _device(ctx, off, mz, inten, check=False)
     assert ctx.device_errors() & 2
     assert o[2] - o[1] == 0  # the oversized spectrum gets no entries
     want = oracle.preprocess(*_pack([small]), oracle.Params(dim=2048))

@@ -2,8 +2,10 @@
 library's own radix sort: rows by (charge, precursor m/z, library index), so
 that every candidate set is one run of rows. Checked element by element
 against numpy's stable lexsort, with many exact ties (rounded precursors,
-decoys sharing their reference's precursor), signed charges, NaN precursors,
-and sizes around the sort's 4,096-element tiles."""
+decoys sharing their reference's precursor), -0.0 beside +0.0 (equal, so
+ordered by library index), NaN precursors of different payloads (all after
++inf, by library index), signed charges, and sizes around the sort's
+4,096-element tiles."""
 import numpy as np
 import pytest
 
@@ -31,6 +33,11 @@ def test_library_order(n, charge_match):
     rng = np.random.default_rng(n)
     pmz = np.round(rng.uniform(-50.0, 1500.0, n), 1)  # about 15,500 distinct values
     pmz[rng.random(n) < 0.001] = np.nan
+    pmz[3::97] = 0.0
+    pmz[7::89] = -0.0
+    nan2 = np.array([0x7FF4000000000001, 0xFFF8000000000000], np.uint64).view(np.float64)
+    pmz[11::131] = nan2[0]
+    pmz[13::127] = nan2[1]
     charge = rng.integers(-3, 6, n).astype(np.int8)
     idx = np.arange(n)
     with h.Context(h.Params(dim=512, charge_match=charge_match)) as ctx:

@@ -134,3 +134,51 @@ def test_round_hidden_forward_differs_only_by_bf16_rounding():
     rel = np.abs(b["h"][nz] - a["h"][nz]) / np.abs(a["h"][nz])
     assert rel.max() <= 2.0 ** -8 and (b["h"][~nz] == 0).all()
     assert not np.array_equal(a["h"], b["h"])
+
+
+def test_round_e4m3_known_values():
+    """E4M3 keeps 3 fraction bits: 1 + 1/16 lies halfway between 1 and 1.125
+    and goes to the even one (1); 1 + 3/16 goes to 1.25; 3.3 = 1.65 * 2 is
+    nearest 1.625 * 2; 17 is halfway between 16 and 18 (even: 16), 17.5 is
+    nearer 18; 448 is the largest value and larger ones saturate; below 2^-6
+    the spacing is 2^-9 (2^-10 is halfway between 0 and 2^-9: 0; 3 * 2^-10
+    goes to 2^-8; 7.5 * 2^-9 goes to 8 * 2^-9 = 2^-6)."""
+    x = np.array([1.0, 1 + 1 / 16, 1 + 3 / 16, 1.07, -3.3, 17.0, 17.5, 448.0, 500.0, -1e6,
+                  2.0 ** -6, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -10, 7.5 * 2.0 ** -9, 0.0])
+    want = np.array([1.0, 1.0, 1.25, 1.125, -3.25, 16.0, 18.0, 448.0, 448.0, -448.0,
+                     2.0 ** -6, 2.0 ** -9, 0.0, 2.0 ** -8, 2.0 ** -6, 0.0])
+    assert np.array_equal(mlp.round_e4m3(x), want)
+    codes = mlp.e4m3_code(x)
+    assert [int(c) for c in codes] == [0x38, 0x38, 0x3A, 0x39, 0xC5, 0x58, 0x59, 0x7E, 0x7E,
+                                       0xFE, 0x08, 0x01, 0x00, 0x02, 0x08, 0x00]
+
+
+def test_e4m3_codes_decode_to_their_values():
+    """Every finite code decodes (from the format's definition) to a value
+    that rounds back to the same code, and the values are strictly
+    increasing in the code over the positive half."""
+    c = np.arange(0x7F)
+    e, m = c >> 3, c & 7
+    val = np.where(e > 0, np.ldexp(1.0 + m / 8.0, e - 7), m * 2.0 ** -9)
+    assert np.all(np.diff(val) > 0) and val[-1] == 448.0
+    assert np.array_equal(mlp.e4m3_code(val), c.astype(np.uint8))
+    assert np.array_equal(mlp.e4m3_code(-val[1:]), (c[1:] | 0x80).astype(np.uint8))
+    assert np.array_equal(mlp.round_e4m3(val), val)
+    # midpoints between neighbours go to the code with the even fraction
+    mid = (val[1:] + val[:-1]) / 2
+    want = np.where(c[:-1] % 2 == 0, c[:-1], c[1:])
+    assert np.array_equal(mlp.e4m3_code(mid), want.astype(np.uint8))
+
+
+def test_scoring_embeddings_relative_error():
+    """Scaled by 16, a unit embedding's components lie in E4M3's range; the
+    scoring value differs from e by at most 2^-4 of its magnitude in the
+    normal range (half a unit in the last of 3 fraction bits) and by at most
+    2^-10 / 16 absolutely below it."""
+    rng = np.random.default_rng(2)
+    e = rng.normal(size=(50, 256))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    s = mlp.scoring_embeddings(e)
+    big = np.abs(16 * e) >= 2.0 ** -6
+    assert np.all(np.abs(s - e)[big] <= 2.0 ** -4 * np.abs(e)[big])
+    assert np.all(np.abs(s - e)[~big] <= 2.0 ** -10 / 16)
