@@ -265,6 +265,27 @@ homs_status homs_search_window(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv
                                int32_t *d_out_dist, void *stream);
 
 /*
+ * homs_search_window without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, results and errors as
+ * homs_search_window (the same kernels run), but the per-call scratch (window
+ * bounds, query order, result keys) lives in a static device array of 8 MiB
+ * that the library holds on each GPU it runs on until the process ends; the
+ * call makes no hipMalloc, hipFree or other allocating call and records no
+ * profiling events.
+ * Limit: nq <= HOMS_NOALLOC_MAX_QUERIES; larger nq returns HOMS_E_INVALID.
+ * Every call on one GPU (from any context) shares that GPU's array, and it
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams, threads or contexts) race and must be serialised by the caller.
+ * Asynchronous on `stream`.
+ */
+#define HOMS_NOALLOC_MAX_QUERIES 131072
+homs_status homs_search_window_noalloc(homs_ctx *ctx, int64_t nq, const uint32_t *d_q_hv,
+                                       const double *d_q_pmz, const int8_t *d_q_charge,
+                                       const homs_window *win, int32_t engine,
+                                       int64_t *d_out_idx, int32_t *d_out_dist, void *stream);
+
+/*
  * Cascade search, Section 3.4, with target-decoy FDR filtering (Section 2.1;
  * the fixed 1% level of Section 4.1 is fdr_level = 0.01). Stage 1 searches
  * every query with the narrow window; stage 2 searches, with the wide

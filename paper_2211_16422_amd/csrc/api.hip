@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -160,6 +161,33 @@ homs_status ensure_workspace(homs_ctx* c, size_t bytes, hipStream_t s)
 }
 
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Scratch of homs_search_window_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends. Host code never passes the symbol
+// itself to a kernel (on the host it is only a stand-in): the device address
+// of each GPU's copy is taken once per device with hipGetSymbolAddress while
+// that device is current, and that address is what the kernels get.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;  // by device ordinal; nullptr until looked up
+
+// The device address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, void** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)device >= g_scratch_addr.size()) g_scratch_addr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 // Per-call search scratch carved out of the workspace.
 struct SearchScratch {
@@ -348,6 +376,7 @@ homs_status homs_create(const homs_params* p, int32_t device, homs_ctx** out)
     if (e == hipSuccess) e = hipMemcpy(c->d_id, id.data(), id.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_level, lv.data(), lv.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->d_err, 0, 256);
+    if (e == hipSuccess) e = scratch_address(device, &c->noalloc_scratch);
     if (e != hipSuccess) {
         std::string msg = std::string("context setup: ") + hipGetErrorString(e);
         homs_destroy(c);
@@ -574,12 +603,15 @@ int engine_tile(int32_t engine)
 // may keep their own buffers after that region.
 homs_status run_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv, const double* d_q_pmz,
                        const int8_t* d_q_charge, const homs_window* win, int32_t engine,
-                       int64_t* d_out_idx, int32_t* d_out_dist, hipStream_t s)
+                       int64_t* d_out_idx, int32_t* d_out_dist, hipStream_t s,
+                       void* scratch_base = nullptr, bool profile = true)
 {
     const int tile = engine_tile(engine);
-    SearchScratch w = carve(c->ws.ptr, nq, tile);
+    SearchScratch w = carve(scratch_base ? scratch_base : c->ws.ptr, nq, tile);
+    // without profiling no event is created or recorded
+    auto mark = [&]() -> hipEvent_t { return profile ? prof_mark(c, s) : nullptr; };
 
-    hipEvent_t e0 = prof_mark(c, s);
+    hipEvent_t e0 = mark();
     HIP_TRY(c, homs::launch_window_bounds(c, nq, d_q_pmz, d_q_charge, win->kind, win->value,
                                           nullptr, nullptr, w.lo, w.hi, s),
             "window kernel");
@@ -591,7 +623,7 @@ homs_status run_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv, const do
             "tile bounds kernel");
     HIP_TRY(c, homs::launch_init_keys(nq, w.keys, s), "init keys kernel");
     homs::TilePlan plan;
-    hipEvent_t e1 = prof_mark(c, s);
+    hipEvent_t e1 = mark();
     if (engine == HOMS_ENGINE_POPCOUNT)
         HIP_TRY(c, homs::launch_search_popcount(c, nq, d_q_hv, qperm, w.lo, w.hi, w.tile_lo,
                                                 w.tile_hi, plan, w.keys, s),
@@ -604,9 +636,9 @@ homs_status run_search(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv, const do
                                             qperm, w.lo, w.hi, w.tile_lo, w.tile_hi, w.qoff, w.keys,
                                             s),
                 "MFMA search kernel");
-    hipEvent_t e2 = prof_mark(c, s);
+    hipEvent_t e2 = mark();
     HIP_TRY(c, homs::launch_finalize(nq, w.keys, d_out_idx, d_out_dist, s), "finalize kernel");
-    hipEvent_t e3 = prof_mark(c, s);
+    hipEvent_t e3 = mark();
     prof_span(c, e0, e1, homs::kProfPrep);
     prof_span(c, e1, e2, homs::kProfSearch);
     prof_span(c, e2, e3, homs::kProfPrep);
@@ -637,6 +669,32 @@ homs_status homs_search_window(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
     if (homs_status st = ensure_workspace(c, search_scratch_bytes(nq, engine_tile(engine)), s))
         return st;
     return run_search(c, nq, d_q_hv, d_q_pmz, d_q_charge, win, engine, d_out_idx, d_out_dist, s);
+}
+
+homs_status homs_search_window_noalloc(homs_ctx* c, int64_t nq, const uint32_t* d_q_hv,
+                                       const double* d_q_pmz, const int8_t* d_q_charge,
+                                       const homs_window* win, int32_t engine,
+                                       int64_t* d_out_idx, int32_t* d_out_dist, void* stream)
+{
+    if (homs_status s = usable(c)) return s;
+    std::string why;
+    if (!window_valid(win, &why)) return fail(c, HOMS_E_INVALID, why);
+    if (!engine_valid(engine)) return fail(c, HOMS_E_INVALID, "unknown engine");
+    if (!c->lib_valid) return fail(c, HOMS_E_STATE, "no encoded library");
+    if (nq < 0 || nq > HOMS_NOALLOC_MAX_QUERIES)
+        return fail(c, HOMS_E_INVALID,
+                    "nq out of range for homs_search_window_noalloc (at most " +
+                        std::to_string(HOMS_NOALLOC_MAX_QUERIES) + " queries)");
+    if (search_scratch_bytes(nq, engine_tile(engine)) > kNoAllocScratchBytes)
+        return fail(c, HOMS_E_INVALID, "nq needs more than the static scratch holds");
+    if (nq == 0) return HOMS_OK;
+    if (!d_q_hv || !d_q_pmz || !d_q_charge || !d_out_idx || !d_out_dist)
+        return fail(c, HOMS_E_INVALID, "NULL device pointer");
+    if (!aligned16(d_q_hv)) return fail(c, HOMS_E_INVALID, "d_q_hv must be 16-byte aligned");
+    if (!c->noalloc_scratch) return fail(c, HOMS_E_STATE, "static scratch not set up");
+    DeviceGuard g(c->device);
+    return run_search(c, nq, d_q_hv, d_q_pmz, d_q_charge, win, engine, d_out_idx, d_out_dist,
+                      (hipStream_t)stream, c->noalloc_scratch, false);
 }
 
 homs_status homs_preprocess_device(homs_ctx* c, int64_t n, const int64_t* d_offsets,

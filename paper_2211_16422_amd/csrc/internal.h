@@ -79,6 +79,7 @@ struct homs_ctx {
     homs::BatchedConfig batched;
     homs::GraphCache graph;
     hipStream_t capture_stream = nullptr;
+    void* noalloc_scratch = nullptr;  // device address of this device's static scratch
     bool dead = false;
     std::string err;
 };

@@ -40,6 +40,9 @@ ENGINE_MFMA_I8 = 1
 ENGINE_MFMA_F8 = 2
 ENGINE_MFMA_F4 = 3
 
+# largest nq of homs_search_window_noalloc (HOMS_NOALLOC_MAX_QUERIES)
+NOALLOC_MAX_QUERIES = 131072
+
 ENCODING_ID_LEVEL = 0
 ENCODING_RANDOM_ID = 1
 ENCODING_LSH = 2
@@ -96,6 +99,8 @@ _sig("homs_library_export", [_P, _P, _P])
 _sig("homs_library_order", [_P, _P, _P])
 _sig("homs_window_bounds", [_P, _i64, _P, _P, ctypes.POINTER(_Window), _P, _P, _P])
 _sig("homs_search_window", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P, _P])
+_sig("homs_search_window_noalloc", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window), _i32, _P, _P,
+                                    _P])
 _sig("homs_preprocess_device", [_P, _i64, _P, _P, _P, _P, _P, _P, _P])
 _sig("homs_cascade_search", [_P, _i64, _P, _P, _P, ctypes.POINTER(_Window),
                              ctypes.POINTER(_Window), _i32, _P, ctypes.c_double, _P, _P, _P, _P,
@@ -133,7 +138,7 @@ EXPORTED = ["homs_params_default", "homs_num_bins", "homs_status_string", "homs_
             "homs_get_codebook", "homs_encode_queries", "homs_encode_library",
             "homs_library_size", "homs_library_export", "homs_library_order",
             "homs_window_bounds",
-            "homs_search_window", "homs_cascade_search", "homs_preprocess_device",
+            "homs_search_window", "homs_search_window_noalloc", "homs_cascade_search", "homs_preprocess_device",
             "homs_debug_distances",
             "homs_device_errors",
             "homs_profile_enable", "homs_profile_read", "homs_batched_config_get",
@@ -453,6 +458,24 @@ class Context:
             out_dist = torch.empty(nq, dtype=torch.int32, device=self.device)
         w = self._win(kind, value)
         self._ck(_lib.homs_search_window(
+            self._h, nq, _dptr(q_hv, torch.int32, "q_hv", self.device),
+            _dptr(pmz, torch.float64, "pmz", self.device),
+            _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(w), engine,
+            _dptr(out_idx, torch.int64, "out_idx", self.device),
+            _dptr(out_dist, torch.int32, "out_dist", self.device), _stream(self.device)))
+        return out_idx, out_dist
+
+    def search_window_noalloc(self, q_hv, pmz, charge, out_idx, out_dist, kind=TOL_DA,
+                              value=500.0, engine=ENGINE_POPCOUNT):
+        """homs_search_window_noalloc: homs_search_window with its scratch in the
+        library's static device array (no allocation; nq <= NOALLOC_MAX_QUERIES);
+        the caller passes the outputs."""
+        import torch
+        nq = pmz.shape[0]
+        if q_hv.shape != (nq, self.words):
+            raise ValueError("q_hv must be [nq, D/32]")
+        w = self._win(kind, value)
+        self._ck(_lib.homs_search_window_noalloc(
             self._h, nq, _dptr(q_hv, torch.int32, "q_hv", self.device),
             _dptr(pmz, torch.float64, "pmz", self.device),
             _dptr(charge, torch.int8, "charge", self.device), ctypes.byref(w), engine,

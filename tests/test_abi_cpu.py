@@ -98,3 +98,9 @@ def test_create_without_device_fails_cleanly(h):
     with pytest.raises(h.HomsError) as e:
         h.Context(h.Params(dim=512))
     assert e.value.status in (h.HOMS_E_DEVICE, h.HOMS_E_INVALID)
+
+
+def test_noalloc_limit_matches_header(h):
+    text = open(os.path.join(ROOT, "include", "hyperoms.h")).read()
+    m = re.search(r"#define\s+HOMS_NOALLOC_MAX_QUERIES\s+(\d+)", text)
+    assert m and int(m.group(1)) == h.NOALLOC_MAX_QUERIES
