@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
 MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
-                    ("mfma_fp4", "fb4f358d3740897a"): 2.6084e+11}
+                    ("mfma_fp4", "210401662af5007c"): 2.6084e+11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
@@ -524,6 +524,19 @@ def exhaustive_times(ctx, h, q_hv, q_pmz, q_ch, reps=3):
     return out, res
 
 
+def mean_bipolar(ctx, dim, n_sample=65536, seed=3):
+    """Mean bipolar hypervector (bit 0 -> +1, bit 1 -> -1) of a random sample
+    of library rows: the centre of the training-free sketch baseline."""
+    import torch
+    rows = ctx.library_export()
+    n = rows.shape[0]
+    pick = np.sort(np.random.default_rng(seed).choice(n, size=min(n_sample, n), replace=False))
+    sub = rows[torch.from_numpy(pick).to(rows.device)].cpu().numpy().view(np.uint8)
+    del rows
+    bits = np.unpackbits(sub, axis=1, bitorder="little")[:, :dim]
+    return 1.0 - 2.0 * bits.mean(axis=0)
+
+
 def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
     """Learned shortlist (an MLP D -> 1024 -> 256 trained on the GPU through
     homs_model_train on (training query, exact top-1) pairs; per query the
@@ -573,7 +586,9 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
 
     agree0, _ = evaluate("untrained")
     model.set_weights(h.sketch_weights(D, H, E, seed=7))
-    agree_sketch, fb_sketch = evaluate("training-free sketch")
+    agree_sketch0, _ = evaluate("training-free sketch (uncentred)")
+    model.set_weights(h.sketch_weights(D, H, E, seed=7, center=mean_bipolar(ctx, D)))
+    agree_sketch, fb_sketch = evaluate("training-free sketch (centred)")
     model.set_weights(init)
     t0 = time.perf_counter()
     steps, losses = model.train(t_hv, t_idx, epochs=args.epochs, batch=args.batch, lr=args.lr,
@@ -614,7 +629,8 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
                    "batch": args.batch, "lr": args.lr, "tau": args.tau},
         "comparisons_covered_per_s": pairs / step_s,
         "top1_agreement": agree, "top1_agreement_untrained": agree0,
-        "top1_agreement_training_free_sketch": agree_sketch, "fallback_rate": fbr,
+        "top1_agreement_training_free_sketch": agree_sketch,
+        "top1_agreement_training_free_sketch_uncentred": agree_sketch0, "fallback_rate": fbr,
         "fallback_rate_sketch": fb_sketch,
         "exhaustive_s_warm_median": ex, "speedup_vs_popcount": ex["popcount"] / step_s,
         "speedup_vs_mfma_fp8": ex["mfma_fp8"] / step_s,

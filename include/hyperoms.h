@@ -399,8 +399,9 @@ homs_status homs_device_errors(homs_ctx *ctx, uint32_t *flags, void *stream);
  *  prep_ms: window, ordering and result kernels around the search kernel
  *           (and the query embedding of homs_search_learned), and the
  *           library sort of homs_encode_library;
- *  score_ms/score_launches: the matrix-core scoring kernel of
- *           homs_search_learned (one launch per pass of queries); its time is
+ *  score_ms/score_launches: the matrix-core scoring kernels of
+ *           homs_search_learned (two scoring launches and the threshold
+ *           refinement between them, per pass of queries); their time is
  *           also part of search_ms.
  */
 typedef struct homs_profile {
@@ -531,13 +532,17 @@ homs_status homs_model_library_embeddings(homs_model *model, uint8_t *d_out_fp8,
 
 /*
  * Shortlist search: for each query, the k (1 <= k <= 1024) candidates of its
- * window with the largest scores (ties to the lower library index) are
- * rescored exactly; d_out_idx / d_out_dist are the Hamming top-1 over them
- * (lowest library index among equal distances; -1 / -1 without candidates).
- * d_out_fallback[q] = 1 marks a query whose shortlist could not be formed
- * (its candidate buffer overflowed or a sampled score threshold kept fewer
- * than min(k, window) candidates); its result is the exhaustive window
- * search. d_out_shortlist (optional, [nq][k] int64) receives each query's
+ * window with the largest scores (score = dot product of the two scoring
+ * embeddings, see homs_model_embed_library; ties to the lower library index)
+ * are rescored exactly; d_out_idx / d_out_dist are the Hamming top-1 over
+ * them (lowest library index among equal distances; -1 / -1 without
+ * candidates). Candidates are found with score thresholds (one estimated
+ * from a sample of the window, then one refined from the hits in every
+ * eighth 128-row block of the sorted library). d_out_fallback[q] = 1 marks a
+ * query whose shortlist could not be formed this way (its candidate buffer
+ * overflowed, a threshold kept fewer than min(k, window) candidates, or the
+ * k-th kept candidate scores below the refined threshold); its result is the
+ * exhaustive window search. d_out_shortlist (optional, [nq][k] int64) receives each query's
  * shortlist by descending score, -1 past the window's size and for fallback
  * queries. Same query arguments as homs_search_window. The model's embed size
  * must be 64, 128 or 256 (HOMS_E_UNSUPPORTED otherwise). Asynchronous; grows

@@ -19,11 +19,18 @@
 //     scoring embeddings, fp32 accumulation, 128 library rows x 128
 //     m/z-ordered queries per workgroup) and append in-window pairs at or
 //     above the query's threshold to its buffer of kCapacity 64-bit keys
-//     (order-preserving score << 32 | sorted row);
+//     (order-preserving score << 32 | sorted row), in two passes: pass 0
+//     over every eighth absolute 128-row block with the sampled threshold;
+//     then per query a threshold refined from pass 0's hits (the r-th best
+//     of them, about 4 max(k, 64) window candidates expected above it); pass
+//     1 over the other blocks with the refined threshold, where hits are
+//     rare enough that most tiles need only one ballot;
 //  3. select: sort each buffer in LDS (bitonic, descending) and keep the k
-//     largest keys; a query whose buffer overflowed, or whose sampled
-//     threshold kept fewer than min(k, window) candidates, is flagged for the
-//     exhaustive fallback and gets no shortlist;
+//     largest keys; a query whose buffer overflowed, whose sampled threshold
+//     kept fewer than min(k, window) candidates, or whose k-th kept key
+//     scores below the refined threshold (so that a better candidate of pass
+//     1 could have been missed) is flagged for the exhaustive fallback and
+//     gets no shortlist;
 //  4. rescore: one lane per shortlist entry computes the exact Hamming
 //     distance; the wave minimum of (distance << 32 | library index) is merged
 //     into the query's key;
@@ -320,6 +327,79 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
     if (threadIdx.x == 0) thr[p] = fkey_inv(prefix);
 }
 
+// Library rows are scored in two passes over absolute 128-row blocks: pass 0
+// takes the blocks whose index is a multiple of kPassStride (an evenly spread
+// 1 / kPassStride of every window) with the sampled threshold, pass 1 the
+// others with a threshold refined from pass 0's hits.
+constexpr int64_t kPassStride = 8;
+
+// rows below x (absolute) that lie in pass-0 blocks
+__host__ __device__ inline int64_t pass0_rows_below(int64_t x)
+{
+    const int64_t span = 128 * kPassStride;
+    return (x / span) * 128 + min(x % span, (int64_t)128);
+}
+
+// One workgroup per query of the pass: the refined threshold. Pass 0 kept,
+// from its 1 / kPassStride share of the window, every candidate scoring at
+// or above the sampled threshold; the r-th largest of them, r = ceil(target x
+// share / window) with target = 4 max(k, 64) (about that many window
+// candidates are then expected at or above it), is the threshold of pass 1.
+// Windows kept whole (-inf), a pass-0 buffer that overflowed, or fewer than r
+// pass-0 candidates keep the sampled threshold.
+__global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
+    int64_t q_begin, int k, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    const int64_t* __restrict__ hi, const uint32_t* __restrict__ count,
+    const uint64_t* __restrict__ buf, const float* __restrict__ thr, float* __restrict__ thr2)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ RadixDigit s_rd;
+    const int64_t qp = blockIdx.x;
+    const int64_t p = q_begin + qp;
+    const float t1 = thr[p];
+    const uint32_t qi = qperm[p];
+    const int64_t a = lo[qi], b = hi[qi], w = b - a;
+    const uint32_t cnt = count[qp * kCountStride];
+    const int64_t share = pass0_rows_below(b) - pass0_rows_below(a);
+    const int64_t target = 4 * (int64_t)max(k, 64);
+    const int64_t r64 = w > 0 ? (target * share + w - 1) / w : 0;
+    // uniform
+    if (t1 == -INFINITY || cnt > (uint32_t)kCapacity || r64 < 1 || (int64_t)cnt < r64) {
+        if (threadIdx.x == 0) thr2[p] = t1;
+        return;
+    }
+    const int n = (int)cnt;
+    uint32_t r = (uint32_t)r64;
+    const uint64_t* keys = buf + (size_t)qp * kCapacity;
+    constexpr int kPer = kCapacity / kThreads;
+    uint32_t key[kPer];  // score halves of the keys, in registers
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = (int)threadIdx.x + j * kThreads;
+        key[j] = i < n ? (uint32_t)(keys[i] >> 32) : 0u;
+    }
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = (int)threadIdx.x + j * kThreads;
+            if (i < n && (key[j] & mask) == prefix) atomicAdd(&hist[(key[j] >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const RadixDigit rd = radix_digit(hist, r);
+            if (threadIdx.x == 0) s_rd = rd;
+        }
+        __syncthreads();
+        prefix |= s_rd.digit << shift;
+        mask |= 255u << shift;
+        r -= s_rd.above;
+    }
+    if (threadIdx.x == 0) thr2[p] = fmaxf(t1, fkey_inv(prefix));
+}
+
 // Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
 // cores and appends every in-window pair at or above the query's threshold.
 //
@@ -332,10 +412,12 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // block and the 64 queries of half wn (two 32-query tiles), whose codes are
 // its B operands for the whole chunk (E / 64 steps of 32 bytes per tile), so
 // every A operand read from LDS feeds two matrix instructions. Library rows
-// stream through two LDS buffers filled by direct global-to-LDS loads
-// (global_load_lds_dwordx4, no staging registers) two blocks ahead of their
-// use: one load moves 1 KB (64 lanes x 16 bytes) of a block's rows, so a
-// 128-row block of E-byte rows takes E / 64 loads per wave. The 16-byte piece
+// stream through four LDS buffers filled by direct global-to-LDS loads
+// (global_load_lds_dwordx4, no staging registers): one load moves 1 KB (64
+// lanes x 16 bytes) of a block's rows, so a 128-row block of E-byte rows
+// takes E / 64 loads per wave. Three blocks are in flight while one is
+// scored, and one barrier per block both publishes the landed block and
+// frees the buffer of the block before it. The 16-byte piece
 // p of row R sits at slot p ^ swz(R) of the row, swz(R) = (R / (16 / P)) mod
 // P with P = E / 16 pieces per row, so the 16 rows a quarter-wave reads
 // together land on 16 distinct 16-byte bank groups. The loads are issued
@@ -343,14 +425,16 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
 // drain every outstanding LDS load before any LDS read and cap the prefetch
 // at one block.
 //
-// Epilogue, software-pipelined: the scores of block b - 1 are examined
-// between the matrix instructions of block b (16 positions per block, both
-// query tiles, spread over its E / 64 matrix steps), so that the compares
-// and ballots issue while the matrix core works. When the wave's 32 rows of
-// the block lie inside every window of its queries (the usual case) a
-// position costs one compare and one ballot per tile and is skipped unless
-// some lane hits; otherwise the block's positions are masked row by row after
-// the matrix instructions. Hits go to the wave's own LDS list at positions
+// Epilogue, software-pipelined: two accumulator sets are used in turn, and
+// the scores of block b - 1 are examined right after block b's matrix
+// instructions are issued, so that the compares and ballots run while the
+// matrix core works (the waves leave each barrier together, so no other
+// wave would cover an epilogue placed before them). When the wave's 32 rows of
+// the block lie inside every window of its queries (the usual case), one
+// ballot per query tile on each lane's largest score first tells whether the
+// tile has any hit; only such tiles take a compare and a ballot per position
+// (skipped unless some lane hits). Otherwise the block's positions are masked
+// row by row after the matrix instructions. Hits go to the wave's own LDS list at positions
 // counted from the ballot (no atomics, no global loads), flushed to the
 // per-query global buffers when half full and at the end.
 constexpr int kWaveList = 384;  // LDS entries per wave
@@ -360,6 +444,14 @@ constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0x
 
 typedef int v8i32 __attribute__((ext_vector_type(8)));
 
+__device__ __forceinline__ float max16(const gemm::f32x16& v)
+{
+    const float a = fmaxf(fmaxf(v[0], v[1]), v[2]), b = fmaxf(fmaxf(v[3], v[4]), v[5]);
+    const float c = fmaxf(fmaxf(v[6], v[7]), v[8]), d = fmaxf(fmaxf(v[9], v[10]), v[11]);
+    const float e = fmaxf(fmaxf(v[12], v[13]), v[14]);
+    return fmaxf(fmaxf(fmaxf(a, b), c), fmaxf(fmaxf(d, e), v[15]));
+}
+
 template <int E>
 __global__ __launch_bounds__(512, 1) void collect_kernel(
     int64_t q_begin, int64_t q_end, const uint8_t* __restrict__ q_sorted8,
@@ -367,7 +459,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
     const uint8_t* __restrict__ lib_emb8, uint32_t* __restrict__ count,
-    uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks)
+    uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks, int pass)
 {
     using namespace gemm;
     constexpr int KS = E / 64;                    // 32 x 32 x 64 steps
@@ -377,8 +469,9 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     constexpr int NW = 8;                         // waves
     constexpr int NL = E / 64;                    // direct loads per wave per block
     constexpr float kScoreScale2 = kScoreScale * kScoreScale;
+    constexpr int kBufs = 4;                      // LDS block buffers: kBufs blocks in flight
     static_assert(KS * PPK == 16 && NL >= 1, "E in {64, 128, 256}");
-    __shared__ __attribute__((aligned(16))) uint8_t sA[2][128 * E];
+    __shared__ __attribute__((aligned(16))) uint8_t sA[kBufs][128 * E];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
     // Chunks are fixed row ranges of the sorted library, clipped to the
@@ -397,16 +490,31 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     if (c0 >= c1) return;
     const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 3, wn = w >> 2;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
-    const int nblk = (int)((c1 - c0 + 127) / 128);
+    // This pass's absolute 128-row blocks meeting [c0, c1): pass 0 the
+    // multiples of kPassStride, pass 1 the others. Rows of a block below c0
+    // lie below every window of the tile (c0 is the chunk's first row or the
+    // tile's lowest window start) and are masked like any row outside a window.
+    const int64_t g_lo = c0 / 128, g_hi = (c1 + 127) / 128;
+    const int64_t f0 = (g_lo + kPassStride - 1) / kPassStride * kPassStride;
+    const int64_t n0 = f0 < g_hi ? (g_hi - 1 - f0) / kPassStride + 1 : 0;
+    const int nblk = (int)(pass == 0 ? n0 : (g_hi - g_lo) - n0);
+    const int64_t skip1 = g_lo % kPassStride == 0 ? 0 : g_lo % kPassStride - 1;
+    auto block_row = [&](int b) -> int64_t {  // first (absolute) row of block b
+        if (pass == 0) return (f0 + (int64_t)b * kPassStride) * 128;
+        const int64_t i = b + skip1;
+        return ((g_lo / kPassStride + i / (kPassStride - 1)) * kPassStride + 1 +
+                i % (kPassStride - 1)) * 128;
+    };
+    if (nblk == 0) return;
 
-    // rows [c0 + 128 b, + 128) into sA[b & 1]: load x of wave w fills bytes
+    // rows [block_row(b), + 128) into sA[b % kBufs]: load x of wave w fills bytes
     // [1024 (NL w + x), + 1024) of the buffer (the destination of a direct
     // load is M0 + 16 x lane), lane l the slot of row R = o / E, o the byte
     // offset of the lane, with the row's piece (slot ^ swz(R)); rows past c1
     // repeat the last row
     auto issue = [&](int b) {
-        const int64_t mb = c0 + (int64_t)b * 128;
-        const uint32_t base = (uint32_t)(uintptr_t)&sA[b & 1][0];
+        const int64_t mb = block_row(b);
+        const uint32_t base = (uint32_t)(uintptr_t)&sA[b % kBufs][0];
         const uint8_t* gbase = lib_emb8 + (size_t)mb * E;  // wave-uniform
         const int last = (int)min((int64_t)127, c1 - 1 - mb);
 #pragma unroll
@@ -471,8 +579,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // wait for them is left inside the loop, where it would also wait for the
     // prefetched blocks (vmcnt counts in issue order).
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-    issue(0);
-    if (nblk > 1) issue(1);
+    for (int b = 0; b < kBufs - 1 && b < nblk; ++b) issue(b);
 
     // the wave's LDS hit list and its flush to the per-query global buffers
     uint32_t wcount = 0;  // wave-uniform
@@ -529,91 +636,113 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // wb + i with wb = the block's first row + 32 wr: gl + roff(r) with
     // gl = wb + 4 (l / 32).
     auto roff = [](int r) -> uint32_t { return (uint32_t)(8 * (r >> 2) + (r & 3)); };
-    f32x16 acc[2], prev[2];
-    bool have_prev = false, prev_fast = false;
-    uint32_t gl_prev = 0;
-    for (int b = 0; b <= nblk; ++b) {
-        if (b < nblk) {
-            // block b has landed: the loads of block b + 1 (if any) may stay in flight
-            if (b + 1 < nblk)
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm(NL));
-            else
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-            __syncthreads();
-            prev[0] = acc[0];
-            prev[1] = acc[1];
-            acc[0] = acc[1] = f32x16{0};
-            const uint8_t* Ab = sA[b & 1];
-            if (have_prev && prev_fast) {
+    // The scores of a scored block, examined while the next block's matrix
+    // instructions run: gl = the row of accumulator register 0 in this lane,
+    // fast = every row of the wave lies inside every window of its queries.
+    auto examine = [&](const f32x16(&a)[2], uint32_t gl, bool fast) {
+        if (fast) {
+            // which query tiles have a hit at all: the largest of a lane's 16
+            // scores (one query, 16 rows) against its threshold, one ballot
+            // per tile; only those take a compare and a ballot per position
+            bool hit[2];
 #pragma unroll
-                for (int kk = 0; kk < KS; ++kk) {
-                    const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
-                    const uint4 u1 = *(const uint4*)(Ab + aoff[kk][1]);
-                    const v8i32 av = {(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
-                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
-                    acc[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av, bq[0][kk], acc[0], 0, 0, 0, 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av, bq[1][kk], acc[1], 0, 0, 0, 0, 0, 0);
+            for (int j = 0; j < 2; ++j) hit[j] = __ballot(max16(a[j]) >= qthr[j]) != 0;
+            if (hit[0] || hit[1]) {
 #pragma unroll
-                    for (int q = 0; q < PPK; ++q) {
-                        const int r = kk * PPK + q;
-                        const uint32_t g = gl_prev + roff(r);
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t g = gl + roff(r);
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
-                            const float sc = prev[j][r];
-                            const uint64_t m = __ballot(sc >= qthr[j]);
-                            if (m != 0) append(m, sc >= qthr[j], sc, g, j);
-                        }
+                    for (int j = 0; j < 2; ++j) {
+                        if (!hit[j]) continue;
+                        const float sc = a[j][r];
+                        const uint64_t m = __ballot(sc >= qthr[j]);
+                        if (m != 0) append(m, sc >= qthr[j], sc, g, j);
                     }
                 }
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < KS; ++kk) {
-                    const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
-                    const uint4 u1 = *(const uint4*)(Ab + aoff[kk][1]);
-                    const v8i32 av = {(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
-                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
-                    acc[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av, bq[0][kk], acc[0], 0, 0, 0, 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av, bq[1][kk], acc[1], 0, 0, 0, 0, 0, 0);
-                }
             }
-            __syncthreads();  // every wave is done reading sA[b & 1]
-            if (b + 2 < nblk) issue(b + 2);
-        } else {
-            prev[0] = acc[0];
-            prev[1] = acc[1];
-        }
-        if (have_prev && (!prev_fast || b == nblk)) {
-            // the previous block's positions not examined above
+        } else {  // window or chunk edge inside the wave's rows: per-row masks
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t g = gl_prev + roff(r);
+                const uint32_t g = gl + roff(r);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const float sc = prev[j][r];
-                    const bool ok = sc >= qthr[j] &&
-                                    (prev_fast || (g < e1 && g >= qlo[j] && g < qhi[j]));
+                    const float sc = a[j][r];
+                    const bool ok = sc >= qthr[j] && g < e1 && g >= qlo[j] && g < qhi[j];
                     const uint64_t m = __ballot(ok);
                     if (m != 0) append(m, ok, sc, g, j);
                 }
             }
         }
-        if (wcount > kWaveList / 2) flush();  // wave-uniform, at most once per block
-        if (b < nblk) {
-            // block b's scores are examined during block b + 1 (or after the loop)
-            have_prev = true;
-            const uint32_t wb = (uint32_t)(c0 + (int64_t)b * 128) + wr * 32;
-            gl_prev = wb + 4u * (uint32_t)(l >> 5);
-            bool inside = wb + 32 <= e1;
+    };
+    auto block_info = [&](int b, uint32_t& gl, bool& fast) {
+        const uint32_t wb = (uint32_t)block_row(b) + wr * 32;
+        gl = wb + 4u * (uint32_t)(l >> 5);
+        bool inside = wb + 32 <= e1;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                inside = inside && (!qok[j] || (wb >= qlo[j] && wb + 32 <= qhi[j]));
-            prev_fast = __ballot(!inside) == 0;
+        for (int j = 0; j < 2; ++j)
+            inside = inside && (!qok[j] || (wb >= qlo[j] && wb + 32 <= qhi[j]));
+        fast = __ballot(!inside) == 0;
+    };
+    // Block b has landed (the loads of up to kBufs - 2 later blocks may stay
+    // in flight); after the barrier every wave is done with block b - 1, whose
+    // buffer takes block b + kBufs - 1. One barrier per block.
+    auto wait_block = [&](int b) {
+        const int ahead = min(kBufs - 2, nblk - 1 - b);
+        static_assert(kBufs == 4, "one wait per number of blocks ahead");
+        if (ahead >= 2)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * NL));
+        else if (ahead == 1)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(NL));
+        else
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        __syncthreads();
+        if (b + kBufs - 1 < nblk) issue(b + kBufs - 1);
+    };
+    // block b's matrix instructions: every A operand read first, then the
+    // E / 64 steps of both query tiles
+    auto score = [&](int b, f32x16(&a)[2]) {
+        const uint8_t* Ab = sA[b % kBufs];
+        v8i32 av[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
+            const uint4 u1 = *(const uint4*)(Ab + aoff[kk][1]);
+            av[kk] = v8i32{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                           (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+        }
+        a[0] = a[1] = f32x16{0};
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            a[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[kk], bq[0][kk], a[0], 0, 0,
+                                                                   0, 0, 0, 0);
+            a[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[kk], bq[1][kk], a[1], 0, 0,
+                                                                   0, 0, 0, 0);
+        }
+    };
+
+    // Two accumulator sets in turn: block b scores into one while block
+    // b - 1's scores, in the other, are examined.
+    f32x16 accA[2], accB[2];
+    uint32_t glA = 0, glB = 0;
+    bool fastA = false, fastB = false;
+    for (int b = 0; b < nblk; b += 2) {
+        wait_block(b);
+        score(b, accA);
+        if (b > 0) examine(accB, glB, fastB);
+        block_info(b, glA, fastA);
+        if (wcount > kWaveList / 2) flush();  // wave-uniform
+        if (b + 1 < nblk) {
+            wait_block(b + 1);
+            score(b + 1, accB);
+            examine(accA, glA, fastA);
+            block_info(b + 1, glB, fastB);
+            if (wcount > kWaveList / 2) flush();
         }
     }
+    if (nblk & 1)
+        examine(accA, glA, fastA);
+    else
+        examine(accB, glB, fastB);
     flush();
 }
 
@@ -644,7 +773,7 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int n = (int)min(cnt, (uint32_t)kCapacity);
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
-    const bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
+    bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
     const uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
     const int kk = min(k, n);  // keys kept
     // The scoring kernel stored (score << 32 | sorted row); the result keys
@@ -734,6 +863,10 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
         for (int i = m + threadIdx.x; i < np; i += blockDim.x) s_sel[i] = 0ull;
         __syncthreads();
         if (np > 1) bitonic_desc(s_sel, np);
+        // Every window candidate scoring at or above thr is in the buffer
+        // (pass 1 kept those, pass 0 kept more of its blocks); the kk kept
+        // keys are the window's best only if the kk-th scores at least thr.
+        if (sampled && (uint32_t)(s_sel[kk - 1] >> 32) < fkey(thr[p])) bad = true;
     }
     int64_t* out = shortlist + (size_t)qi * k;
     for (int i = threadIdx.x; i < k; i += blockDim.x)
@@ -850,7 +983,7 @@ size_t learned_scratch_bytes(int64_t nq, int64_t E, LearnedScratchPlan* plan)
     pl.batch = std::max<int64_t>(pl.batch, kTileQ);
     if (plan) *plan = pl;
     const int64_t tiles = pl.batch / kTileQ;
-    return al(nq * E * 2) + al(nq * E) + al(nq * 4) + al(pl.batch * 4 * kCountStride) +
+    return al(nq * E * 2) + al(nq * E) + 2 * al(nq * 4) + al(pl.batch * 4 * kCountStride) +
            al(pl.batch * (int64_t)kCapacity * 8) +
            2 * al(tiles * 8) + al(tiles * sizeof(SampleGrid)) + al(pl.batch * (int64_t)kSample * 4);
 }
@@ -872,6 +1005,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     uint8_t* q_sorted8 = (uint8_t*)p;
     p += al(nq * E);
     float* thr = (float*)p;
+    p += al(nq * 4);
+    float* thr2 = (float*)p;
     p += al(nq * 4);
     uint32_t* count = (uint32_t*)p;
     p += al(plan.batch * 4 * kCountStride);
@@ -908,20 +1043,28 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const int64_t cwg = tiles * ((max_chunks + 7) / 8) * 8;
         if (cwg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
         const uint32_t cgrid = (uint32_t)cwg;
-        if (E == 256)
-            collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb8, count, buf, tiles,
-                                                      max_chunks);
-        else if (E == 128)
-            collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
-                                                      thi, m->lib_emb8, count, buf, tiles,
-                                                      max_chunks);
-        else
-            collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, thr, tlo,
-                                                     thi, m->lib_emb8, count, buf, tiles,
-                                                     max_chunks);
+        // pass 0 with the sampled threshold, the refined threshold from its
+        // hits, pass 1 with the refined one (same buffers, appended)
+        for (int pass = 0; pass < 2; ++pass) {
+            const float* t = pass == 0 ? thr : thr2;
+            if (E == 256)
+                collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                          tlo, thi, m->lib_emb8, count, buf,
+                                                          tiles, max_chunks, pass);
+            else if (E == 128)
+                collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                          tlo, thi, m->lib_emb8, count, buf,
+                                                          tiles, max_chunks, pass);
+            else
+                collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                         tlo, thi, m->lib_emb8, count, buf,
+                                                         tiles, max_chunks, pass);
+            if (pass == 0)
+                refine_threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi,
+                                                                          count, buf, thr, thr2);
+        }
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
-        select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr, qperm, lo, hi,
+        select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr2, qperm, lo, hi,
                                                           c->lib.orig, shortlist, fallback);
         rescore_kernel<<<(uint32_t)((nb + 3) / 4), kThreads, 0, s>>>(
             b0, b1, k, c->words, q_hv, qperm, shortlist, c->lib.slot, c->lib.hv, keys);

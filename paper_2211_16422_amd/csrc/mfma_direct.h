@@ -54,10 +54,29 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // f8f6f4 matrix instruction; kFmtI8 selects the int8 instruction
 constexpr int kFmtF8 = 0, kFmtF4 = 4, kFmtI8 = 8;
 
-constexpr int WR = 2, WQ = 4, TR = 4, TQ = 2;
-constexpr int kThreads = 64 * WR * WQ;   // 512
-constexpr int kRows = WR * TR * 32;      // library rows per block step (256)
-constexpr int kQueries = WQ * TQ * 32;   // queries per tile (256)
+// Wave layouts of the 256-row x 256-query workgroup tile: WR x WQ waves,
+// each owning TR x TQ matrix tiles of 32 x 32 (TR 32-row tiles of library
+// rows, TQ 32-query tiles). An expanded library operand feeds TQ matrix
+// instructions and an expanded query operand TR of them.
+template <int WR_, int WQ_, int TR_, int TQ_>
+struct Layout {
+  static constexpr int WR = WR_, WQ = WQ_, TR = TR_, TQ = TQ_;
+  static constexpr int NW = WR * WQ;
+  static constexpr int kThreads = 64 * NW;
+  static constexpr int kRows = WR * TR * 32;
+  static constexpr int kQueries = WQ * TQ * 32;
+  static constexpr int kLoadRows = 256 / NW;  // rows of each operand a wave moves per stage
+  static_assert(kRows == 256 && kQueries == 256, "256 x 256 workgroup tiles");
+};
+// 8 waves (two per SIMD) of 4 x 2 tiles: 8 accumulators of 16 registers
+using Layout8 = Layout<2, 4, 4, 2>;
+// 4 waves (one per SIMD) of 4 x 4 tiles: 16 accumulators (AGPRs), each
+// expanded library operand feeding four matrix instructions
+using Layout4 = Layout<2, 2, 4, 4>;
+
+constexpr int kThreads = Layout8::kThreads;   // 512 (the persistent kernel's layout)
+constexpr int kRows = 256;      // library rows per block step
+constexpr int kQueries = 256;   // queries per tile
 
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
@@ -130,15 +149,15 @@ __device__ __forceinline__ char* stage_lds() {
   __shared__ __attribute__((aligned(16))) char buf[kStageBytes];
   return buf;
 }
-// library indices of each wave's 128 rows of a block, two blocks in flight
+// library indices of each wave's rows of a block, two blocks in flight
 __device__ __forceinline__ uint32_t* orig_lds() {
-  __shared__ __attribute__((aligned(16))) uint32_t buf[2 * WR * WQ * TR * 32];
+  __shared__ __attribute__((aligned(16))) uint32_t buf[2 * Layout8::NW * Layout8::TR * 32];
   return buf;
 }
 
 // qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8
 // and int8)
-template <int F, int kSG, bool kAhead>
+template <int F, int kSG, bool kAhead, class L>
 __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
@@ -146,11 +165,13 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
 {
   constexpr int MR = kRows, NQ = kQueries;
+  constexpr int WR = L::WR, WQ = L::WQ, TR = L::TR, TQ = L::TQ, RPW = L::kLoadRows;
+  static_assert(L::NW * TR <= Layout8::NW * Layout8::TR, "library index buffer");
   constexpr int kRowBytes = kSG * 32;    // bytes of a row per stage
   constexpr int kP = 2 * kSG;            // 16-byte pieces per row and stage
   constexpr int kRPB = 64 / (8 * kSG);   // rows between repeats of the bank pattern
   constexpr int kRPI = 64 / kP;          // rows per direct-load instruction
-  constexpr int kLI = 32 / kRPI;         // instructions per wave and operand (32 rows)
+  constexpr int kLI = RPW / kRPI;        // instructions per wave and operand (RPW rows)
   constexpr int kBuf = (MR + NQ) * kRowBytes;
   static_assert(2 * kBuf <= kStageBytes, "stage buffers");
   const uint32_t D = words * 32;
@@ -183,11 +204,11 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
               : k0 == ~0ull ? -INFINITY
                             : (float)(Q[j] - 2 * (int)(uint32_t)(k0 >> 32));
   }
-  // query rows this lane moves into LDS: rows w * 32 + x * kRPI + l / kP
+  // query rows this lane moves into LDS: rows w * RPW + x * kRPI + l / kP
   const char* qld[kLI];
 #pragma unroll
   for (int x = 0; x < kLI; ++x) {
-    const int64_t qs = tile * NQ + w * 32 + x * kRPI + l / kP;
+    const int64_t qs = tile * NQ + w * RPW + x * kRPI + l / kP;
     const uint32_t qi = qs < nq ? qperm[qs] : qperm[nq - 1];
     qld[x] = (const char*)(q_hv + (size_t)qi * words);
   }
@@ -211,9 +232,9 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
                  "+v"(k4.c66));
 
   // piece loaded by this lane in instruction x: LDS position l % kP of row
-  // w * 32 + x * kRPI + l / kP holds piece position ^ f(row)
+  // w * RPW + x * kRPI + l / kP holds piece position ^ f(row)
   auto lpos = [&](int x) {
-    const uint32_t row = (uint32_t)(w * 32 + x * kRPI + l / kP);
+    const uint32_t row = (uint32_t)(w * RPW + x * kRPI + l / kP);
     return (uint32_t)(l % kP) ^ ((row / kRPB) % kP);
   };
   // Stage S into buffer S % 2: library rows (clamped to the chunk's last
@@ -241,10 +262,10 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const char* gA = (const char*)(lib + (size_t)rb * words);  // uniform
 #pragma unroll
     for (int x = 0; x < kLI; ++x) {
-      const uint32_t row = (uint32_t)(w * 32 + x * kRPI + l / kP);
+      const uint32_t row = (uint32_t)(w * RPW + x * kRPI + l / kP);
       const uint32_t voff = min(row, lim) * words * 4u + sp * kRowBytes + lpos(x) * 16u;
       const uint32_t m0 = __builtin_amdgcn_readfirstlane(
-          (uint32_t)(uintptr_t)(sA + (w * 32 + x * kRPI) * kRowBytes));
+          (uint32_t)(uintptr_t)(sA + (w * RPW + x * kRPI) * kRowBytes));
       asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
                    :
                    : "v"(voff), "s"(gA), "s"(m0)
@@ -254,7 +275,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     for (int x = 0; x < kLI; ++x) {
       const char* src = qld[x] + sp * kRowBytes + lpos(x) * 16u;
       const uint32_t m0 = __builtin_amdgcn_readfirstlane(
-          (uint32_t)(uintptr_t)(sB + (w * 32 + x * kRPI) * kRowBytes));
+          (uint32_t)(uintptr_t)(sB + (w * RPW + x * kRPI) * kRowBytes));
       asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
                    :
                    : "v"(src), "s"(m0)
@@ -442,7 +463,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
 // 4-group stages when D / 256 is a multiple of 4, else 2-group stages;
 // kAhead reads each group's operands one group early (for callers with 24
 // registers to spare)
-template <int F, bool kAhead = false>
+template <int F, bool kAhead = false, class L = Layout8>
 __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
@@ -450,11 +471,11 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
 {
   if (words % 32 == 0)
-    tile_rows_staged<F, 4, kAhead>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff,
-                                   keys);
+    tile_rows_staged<F, 4, kAhead, L>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig,
+                                      qoff, keys);
   else
-    tile_rows_staged<F, 2, kAhead>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig, qoff,
-                                   keys);
+    tile_rows_staged<F, 2, kAhead, L>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig,
+                                      qoff, keys);
 }
 
 }  // namespace mfd

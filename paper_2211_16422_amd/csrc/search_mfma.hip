@@ -43,8 +43,12 @@ namespace {
 constexpr int kXcds = 8, kPatchTiles = 4, kPatchChunks = 8;
 constexpr int kPatch = kPatchTiles * kPatchChunks;
 
+// wave layout of the one-shot kernels
+using DirectLayout = mfd::Layout8;
+
 template <int F>
-__global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t words, int64_t nq,
+__global__ __launch_bounds__(DirectLayout::kThreads, 1) void mfma_direct_kernel(uint32_t words,
+    int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
@@ -63,8 +67,8 @@ __global__ __launch_bounds__(mfd::kThreads, 1) void mfma_direct_kernel(uint32_t 
   const int64_t a64 = max(cidx * chunk, tlo[tile]);
   const int64_t b64 = min(cidx * chunk + chunk, thi[tile]);
   if (a64 >= b64) return;
-  mfd::tile_rows<F, true>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64, (uint32_t)b64,
-                          lib, orig, qoff, keys);
+  mfd::tile_rows<F, true, DirectLayout>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64,
+                                        (uint32_t)b64, lib, orig, qoff, keys);
 }
 
 // The fp4 form's per-query constant Q = -3D/4 + 10 |b|_0 + 2 |b|_1 + 2 |b|_2,
@@ -86,14 +90,13 @@ __global__ __launch_bounds__(256) void fp4_query_offsets_kernel(int64_t nq, uint
   if (l == 0) qoff[q] = s - (int)(3 * words * 8);
 }
 
-constexpr int kMfWR = 2, kMfWQ = 4, kMfTR = 4, kMfTQ = 2;
-constexpr int kMfQueries = kMfWQ * kMfTQ * 32;  // 256 per workgroup
+constexpr int kMfQueries = mfd::kQueries;  // 256 per workgroup
 constexpr int64_t kMfChunk = 4096;
 
 }  // namespace
 
 int search_mfma_tile() { return kMfQueries; }
-int64_t search_mfma_row_pad() { return kMfWR * kMfTR * 32; }
+int64_t search_mfma_row_pad() { return mfd::kRows; }
 
 hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
                                     int32_t* qoff, hipStream_t s)
@@ -111,7 +114,7 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
     const int64_t n_tiles = (nq + kMfQueries - 1) / kMfQueries;
     if (n_tiles <= 0 || c->lib.n <= 0) return hipSuccess;
     const int64_t max_chunks = (c->lib.n + kMfChunk - 1) / kMfChunk;
-    const dim3 block(64 * kMfWR * kMfWQ);
+    const dim3 block(DirectLayout::kThreads);
     const int64_t tile_groups = (n_tiles + kPatchTiles - 1) / kPatchTiles;
     const int64_t chunk_patches = (max_chunks + kPatchChunks - 1) / kPatchChunks;
     const int64_t patches = tile_groups * chunk_patches;

@@ -637,7 +637,8 @@ def to_device_csr(off, bins, levels, device):
 WEIGHT_NAMES = ("W1", "b1", "W2", "b2")
 
 
-def sketch_weights(dim: int, hidden: int, embed: int, seed: int = 0) -> dict:
+def sketch_weights(dim: int, hidden: int, embed: int, seed: int = 0,
+                   center: Optional[np.ndarray] = None) -> dict:
     """Weights under which the network needs no training: it computes a
     signed block-sum sketch (CountSketch) of the bipolar hypervector. The D
     components are dealt at random into `embed` blocks of D / embed, each
@@ -645,7 +646,12 @@ def sketch_weights(dim: int, hidden: int, embed: int, seed: int = 0) -> dict:
     units 2j and 2j + 1 carry ReLU(z_j) and ReLU(-z_j) and W2 takes their
     difference, so z is the sketch exactly (integers of magnitude <= D /
     embed, exact in bfloat16). The shortlist score is the cosine of the two
-    sketches: a training-free shortlist at the same embedding width."""
+    sketches: a training-free shortlist at the same embedding width.
+
+    center (optional, [dim]): a vector subtracted from x before the sketch
+    (through the hidden biases, b1 = -+ the sketch of center), typically the
+    mean bipolar hypervector of the library: spectrum hypervectors share a
+    large common part, and without it the cosines of all pairs crowd near 1."""
     if hidden < 2 * embed or dim % embed:
         raise ValueError("needs hidden >= 2 * embed and embed dividing dim")
     rng = np.random.default_rng(seed)
@@ -658,8 +664,15 @@ def sketch_weights(dim: int, hidden: int, embed: int, seed: int = 0) -> dict:
     W1[2 * rows[:, None] + 1, comp] = -sign
     W2[rows, 2 * rows] = 1.0
     W2[rows, 2 * rows + 1] = -1.0
-    return {"W1": W1, "b1": np.zeros(hidden, np.float32), "W2": W2,
-            "b2": np.zeros(embed, np.float32)}
+    b1 = np.zeros(hidden, np.float32)
+    if center is not None:
+        c = np.asarray(center, np.float64)
+        if c.shape != (dim,):
+            raise ValueError("center must have dim components")
+        m = (sign.astype(np.float64) * c[comp]).sum(axis=1)
+        b1[2 * rows] = -m
+        b1[2 * rows + 1] = m
+    return {"W1": W1, "b1": b1, "W2": W2, "b2": np.zeros(embed, np.float32)}
 
 
 class Model:

@@ -104,3 +104,23 @@ def test_noalloc_limit_matches_header(h):
     text = open(os.path.join(ROOT, "include", "hyperoms.h")).read()
     m = re.search(r"#define\s+HOMS_NOALLOC_MAX_QUERIES\s+(\d+)", text)
     assert m and int(m.group(1)) == h.NOALLOC_MAX_QUERIES
+
+
+def test_sketch_weights_centre(h):
+    """The centred training-free sketch network computes the sketch of x - c
+    (through its hidden biases), checked with the float64 MLP oracle; without
+    a centre its biases are zero and it computes the sketch of x."""
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    D, H, E = 2048, 256, 64
+    c = rng.uniform(-1, 1, D)
+    X = 1.0 - 2.0 * rng.integers(0, 2, (5, D))
+    f64 = lambda w: {k: v.astype(np.float64) for k, v in w.items()}  # noqa: E731
+    plain = h.sketch_weights(D, H, E, seed=3)
+    assert not plain["b1"].any() and not plain["b2"].any()
+    z_c = mlp.forward(f64(h.sketch_weights(D, H, E, seed=3, center=c)), X)["z"]
+    z_shift = mlp.forward(f64(plain), X - c)["z"]
+    assert np.abs(z_c - z_shift).max() < 1e-5
+    # the sketch itself: integer block sums of +-x
+    z = mlp.forward(f64(plain), X)["z"]
+    assert np.array_equal(z, np.round(z)) and np.abs(z).max() <= D // E

@@ -471,7 +471,8 @@ def test_training_raises_agreement():
     """Top-1 agreement with the exhaustive search (Section 3.4) of k = 4 and
     k = 8 shortlists on 1,000 held-out queries, for three networks of the same
     shape: the random initial weights, a training-free signed block-sum sketch
-    of the hypervector (sketch_weights), and the initial weights after
+    of the hypervector minus the library's mean bipolar vector
+    (sketch_weights with a centre), and the initial weights after
     homs_model_train on 16,384 (training query, exact top-1) pairs. Criterion:
     at both k, training removes at least a fifth of the misses of each of the
     other two. The training settings (6 epochs of batches of 256, learning
@@ -495,7 +496,8 @@ def test_training_raises_agreement():
             return np.array(out)
 
         untrained = agreement()
-        s.model.set_weights(h.sketch_weights(s.D, 256, 64, seed=77))
+        centre = mlp.bipolar(s.o_lib, s.D).mean(axis=0)
+        s.model.set_weights(h.sketch_weights(s.D, 256, 64, seed=77, center=centre))
         sketch = agreement()
         s.model.set_weights(s.p)
         t_hv, t_idx = _training_pairs(s)
