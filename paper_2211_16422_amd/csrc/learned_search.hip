@@ -37,6 +37,7 @@
 //  5. fallback: the flagged queries are listed on the device and their whole
 //     windows scanned, one wave per 512-row unit, into the same keys.
 #include <algorithm>
+#include <type_traits>
 
 #include "gemm_bf16.h"
 #include "learned.h"
@@ -452,14 +453,14 @@ __device__ __forceinline__ float max16(const gemm::f32x16& v)
     return fmaxf(fmaxf(fmaxf(a, b), c), fmaxf(fmaxf(d, e), v[15]));
 }
 
-template <int E>
+template <int E, int pass>
 __global__ __launch_bounds__(512, 1) void collect_kernel(
     int64_t q_begin, int64_t q_end, const uint8_t* __restrict__ q_sorted8,
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
     const int64_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_hi,
     const uint8_t* __restrict__ lib_emb8, uint32_t* __restrict__ count,
-    uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks, int pass)
+    uint64_t* __restrict__ buf, int64_t n_tiles, int64_t n_chunks)
 {
     using namespace gemm;
     constexpr int KS = E / 64;                    // 32 x 32 x 64 steps
@@ -498,22 +499,27 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t f0 = (g_lo + kPassStride - 1) / kPassStride * kPassStride;
     const int64_t n0 = f0 < g_hi ? (g_hi - 1 - f0) / kPassStride + 1 : 0;
     const int nblk = (int)(pass == 0 ? n0 : (g_hi - g_lo) - n0);
-    const int64_t skip1 = g_lo % kPassStride == 0 ? 0 : g_lo % kPassStride - 1;
-    auto block_row = [&](int b) -> int64_t {  // first (absolute) row of block b
-        if (pass == 0) return (f0 + (int64_t)b * kPassStride) * 128;
-        const int64_t i = b + skip1;
-        return ((g_lo / kPassStride + i / (kPassStride - 1)) * kPassStride + 1 +
-                i % (kPassStride - 1)) * 128;
-    };
     if (nblk == 0) return;
+    // The pass's blocks in order (32-bit: the library has fewer than 2^31
+    // rows): two walkers, one for the loads (kBufs - 1 blocks ahead) and one
+    // for the epilogue, each stepping to the next block of the pass.
+    const uint32_t first = pass == 0 ? (uint32_t)f0
+                                     : (uint32_t)(g_lo % kPassStride == 0 ? g_lo + 1 : g_lo);
+    auto next_block = [&](uint32_t g) -> uint32_t {
+        if (pass == 0) return g + (uint32_t)kPassStride;
+        g += 1;
+        return g % kPassStride == 0 ? g + 1 : g;
+    };
+    uint32_t g_issue = first, g_epi = first;
 
-    // rows [block_row(b), + 128) into sA[b % kBufs]: load x of wave w fills bytes
-    // [1024 (NL w + x), + 1024) of the buffer (the destination of a direct
-    // load is M0 + 16 x lane), lane l the slot of row R = o / E, o the byte
-    // offset of the lane, with the row's piece (slot ^ swz(R)); rows past c1
-    // repeat the last row
-    auto issue = [&](int b) {
-        const int64_t mb = block_row(b);
+    // rows [128 g, + 128) of the block g_issue points to into sA[b % kBufs]:
+    // load x of wave w fills bytes [1024 (NL w + x), + 1024) of the buffer
+    // (the destination of a direct load is M0 + 16 x lane), lane l the slot
+    // of row R = o / E, o the byte offset of the lane, with the row's piece
+    // (slot ^ swz(R)); rows past c1 repeat the last row
+    auto issue = [&](int b) {  // block b, the one g_issue points to
+        const int64_t mb = (int64_t)g_issue * 128;
+        g_issue = next_block(g_issue);
         const uint32_t base = (uint32_t)(uintptr_t)&sA[b % kBufs][0];
         const uint8_t* gbase = lib_emb8 + (size_t)mb * E;  // wave-uniform
         const int last = (int)min((int64_t)127, c1 - 1 - mb);
@@ -674,8 +680,9 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             }
         }
     };
-    auto block_info = [&](int b, uint32_t& gl, bool& fast) {
-        const uint32_t wb = (uint32_t)block_row(b) + wr * 32;
+    auto block_info = [&](uint32_t& gl, bool& fast) {  // the block g_epi points to
+        const uint32_t wb = g_epi * 128 + wr * 32;
+        g_epi = next_block(g_epi);
         gl = wb + 4u * (uint32_t)(l >> 5);
         bool inside = wb + 32 <= e1;
 #pragma unroll
@@ -687,11 +694,10 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // in flight); after the barrier every wave is done with block b - 1, whose
     // buffer takes block b + kBufs - 1. One barrier per block.
     auto wait_block = [&](int b) {
-        const int ahead = min(kBufs - 2, nblk - 1 - b);
         static_assert(kBufs == 4, "one wait per number of blocks ahead");
-        if (ahead >= 2)
+        if (b + 2 < nblk)
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * NL));
-        else if (ahead == 1)
+        else if (b + 1 < nblk)
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(NL));
         else
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
@@ -729,13 +735,13 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         wait_block(b);
         score(b, accA);
         if (b > 0) examine(accB, glB, fastB);
-        block_info(b, glA, fastA);
+        block_info(glA, fastA);
         if (wcount > kWaveList / 2) flush();  // wave-uniform
         if (b + 1 < nblk) {
             wait_block(b + 1);
             score(b + 1, accB);
             examine(accA, glA, fastA);
-            block_info(b + 1, glB, fastB);
+            block_info(glB, fastB);
             if (wcount > kWaveList / 2) flush();
         }
     }
@@ -1043,26 +1049,27 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const int64_t cwg = tiles * ((max_chunks + 7) / 8) * 8;
         if (cwg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
         const uint32_t cgrid = (uint32_t)cwg;
+        auto collect = [&](auto pass_tag, const float* t) {
+            constexpr int P = decltype(pass_tag)::value;
+            if (E == 256)
+                collect_kernel<256, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                             tlo, thi, m->lib_emb8, count, buf,
+                                                             tiles, max_chunks);
+            else if (E == 128)
+                collect_kernel<128, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                             tlo, thi, m->lib_emb8, count, buf,
+                                                             tiles, max_chunks);
+            else
+                collect_kernel<64, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
+                                                            tlo, thi, m->lib_emb8, count, buf,
+                                                            tiles, max_chunks);
+        };
         // pass 0 with the sampled threshold, the refined threshold from its
         // hits, pass 1 with the refined one (same buffers, appended)
-        for (int pass = 0; pass < 2; ++pass) {
-            const float* t = pass == 0 ? thr : thr2;
-            if (E == 256)
-                collect_kernel<256><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                          tlo, thi, m->lib_emb8, count, buf,
-                                                          tiles, max_chunks, pass);
-            else if (E == 128)
-                collect_kernel<128><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                          tlo, thi, m->lib_emb8, count, buf,
-                                                          tiles, max_chunks, pass);
-            else
-                collect_kernel<64><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                         tlo, thi, m->lib_emb8, count, buf,
-                                                         tiles, max_chunks, pass);
-            if (pass == 0)
-                refine_threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi,
-                                                                          count, buf, thr, thr2);
-        }
+        collect(std::integral_constant<int, 0>{}, thr);
+        refine_threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi, count, buf,
+                                                                  thr, thr2);
+        collect(std::integral_constant<int, 1>{}, thr2);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr2, qperm, lo, hi,
                                                           c->lib.orig, shortlist, fallback);
