@@ -53,7 +53,7 @@ HBM_PEAK_GBS = 8000.0
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy kernel
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
-MEASURED_TRAFFIC = {("popcount", "a5ee47bd0896dc11"): 4.868e12,
+MEASURED_TRAFFIC = {("popcount", "8a0818167cd6a169"): 4.868e12,
                     ("mfma_fp4", "210401662af5007c"): 2.6084e+11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
@@ -213,6 +213,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="learned: training pairs per step")
     ap.add_argument("--lr", type=float, default=3e-5, help="learned: Adam learning rate")
     ap.add_argument("--tau", type=float, default=0.02, help="learned: InfoNCE temperature")
+    ap.add_argument("--init", default="random", choices=["random", "sketch"],
+                    help="learned: initial weights of training (random, or the centred "
+                         "training-free sketch)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -587,9 +590,11 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
     agree0, _ = evaluate("untrained")
     model.set_weights(h.sketch_weights(D, H, E, seed=7))
     agree_sketch0, _ = evaluate("training-free sketch (uncentred)")
-    model.set_weights(h.sketch_weights(D, H, E, seed=7, center=mean_bipolar(ctx, D)))
+    sketch = h.sketch_weights(D, H, E, seed=7, center=mean_bipolar(ctx, D))
+    model.set_weights(sketch)
     agree_sketch, fb_sketch = evaluate("training-free sketch (centred)")
-    model.set_weights(init)
+    if args.init == "random":
+        model.set_weights(init)
     t0 = time.perf_counter()
     steps, losses = model.train(t_hv, t_idx, epochs=args.epochs, batch=args.batch, lr=args.lr,
                                 tau=args.tau, seed=0, losses=True)
@@ -626,7 +631,8 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
         "dtype": "fp8e4m3->f32 (scoring), bf16 (MLP)", "data": "synthetic",
         "config": {"workload": desc + f", MLP {D}-{H}-{E}, k={k}", "pairs_per_step": pairs,
                    "training_pairs": int((t_idx >= 0).sum().item()), "epochs": args.epochs,
-                   "batch": args.batch, "lr": args.lr, "tau": args.tau},
+                   "batch": args.batch, "lr": args.lr, "tau": args.tau,
+                   "init": args.init},
         "comparisons_covered_per_s": pairs / step_s,
         "top1_agreement": agree, "top1_agreement_untrained": agree0,
         "top1_agreement_training_free_sketch": agree_sketch,
