@@ -6,10 +6,17 @@
 // load: the group reads the whole 1 KiB row at D = 8192) and of L_j, binds
 // them with XOR (bit 0 = +1, so the bipolar product is XOR) and adds the
 // 128 resulting bits into bit-sliced counters: plane k holds bit k of the
-// number of -1 components seen so far, updated with a ripple of half adders.
-// The bipolar sum is I = n - 2c (n peaks, c components equal to -1), so the
-// binarised bit (1 unless I > 0) is c >= ceil(n/2), evaluated on the planes
-// with a bit-sliced comparison against that constant.
+// number of -1 components seen so far. Peaks are taken eight at a time: the
+// 16 row loads of a group are issued together (the kernel waits on gathered
+// rows, so loads in flight set its speed), and the eight bound rows enter the
+// counters through a carry-save tree of full adders on the three low planes
+// (the Harley-Seal scheme: planes 0, 1 and 2 take the ones, twos and fours,
+// one carry of weight 8 ripples into the planes above): 21 + 2(P - 3)
+// operations per word for eight peaks (27 at P = 6) where a ripple of half
+// adders takes 2P per peak (96). The last, partial group is masked. The bipolar sum is I = n - 2c
+// (n peaks, c components equal to -1), so the binarised bit (1 unless I > 0)
+// is c >= ceil(n/2), evaluated on the planes with a bit-sliced comparison
+// against that constant.
 //
 // The random-projection baseline of Section 4.2 weights bin i's random row by
 // w = level + 1 instead of binding it with a level vector: S = W - 2c with
@@ -25,16 +32,38 @@ struct U4 {
     uint32_t v[4];
 };
 
-template <int P>
-__device__ __forceinline__ void add_bits(U4 (&c)[P], U4 x)
+// one bit-sliced full adder: a + b + c = sum + 2 carry in every bit position
+// (carry = majority, one bitfield select)
+__device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t& sum,
+                                         uint32_t& carry)
 {
+    const uint32_t u = a ^ b;
+    sum = u ^ c;
+    carry = (u & c) | (~u & a);
+}
+
+// add eight 0/1 slices to the counters (P >= 4): the low three planes act as
+// carry-save accumulators of weight 1, 2 and 4 and the carry of weight 8
+// ripples from plane 3 up, so the count is sum_k plane_k 2^k after every group
+template <int P>
+__device__ __forceinline__ void add_eight(U4 (&c)[P], const U4 (&x)[8])
+{
+    static_assert(P >= 4, "the carry-save tree needs planes 0..3");
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
+    for (int e = 0; e < 4; ++e) {
+        uint32_t ta, tb, fa, fb, y;
+        full_add(c[0].v[e], x[0].v[e], x[1].v[e], c[0].v[e], ta);
+        full_add(c[0].v[e], x[2].v[e], x[3].v[e], c[0].v[e], tb);
+        full_add(c[1].v[e], ta, tb, c[1].v[e], fa);
+        full_add(c[0].v[e], x[4].v[e], x[5].v[e], c[0].v[e], ta);
+        full_add(c[0].v[e], x[6].v[e], x[7].v[e], c[0].v[e], tb);
+        full_add(c[1].v[e], ta, tb, c[1].v[e], fb);
+        full_add(c[2].v[e], fa, fb, c[2].v[e], y);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t carry = c[k].v[e] & x.v[e];
-            c[k].v[e] ^= x.v[e];
-            x.v[e] = carry;
+        for (int k = 3; k < P; ++k) {
+            const uint32_t carry = c[k].v[e] & y;
+            c[k].v[e] ^= y;
+            y = carry;
         }
     }
 }
@@ -81,23 +110,36 @@ __device__ __forceinline__ U4 encode_one(const uint4* __restrict__ id, const uin
 #pragma unroll
         for (int e = 0; e < 4; ++e) c[k].v[e] = 0u;
     uint32_t n_ok = 0;
-    for (int64_t p = a; p < b; ++p) {
-        const int32_t bi = bin[p];
-        const uint32_t lj = level[p];
-        if (bi < 0 || (int64_t)bi >= n_bins || lj >= n_levels) {
-            if (lane == 0) atomicOr(err, kErrRange);
-            continue;
+    bool bad = false;
+    // one group of eight peaks from p on; with `partial`, the slots from b on
+    // re-read peak b - 1 and are masked off. A peak out of range adds nothing
+    // and is not counted (row 0 is loaded in its place and masked off).
+    auto group = [&](int64_t p, bool partial) {
+        U4 x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bool present = !partial || p + i < b;
+            const int64_t q = present ? p + i : b - 1;
+            const int32_t bi = bin[q];
+            const uint32_t lj = level[q];
+            const bool in_range = bi >= 0 && (int64_t)bi < n_bins && lj < n_levels;
+            const bool ok = present && in_range;
+            const uint4 f = id[(ok ? (size_t)bi : 0) * w4 + lane];
+            const uint4 l = lv[(ok ? (size_t)lj : 0) * w4 + lane];
+            const uint32_t m = ok ? ~0u : 0u;
+            x[i].v[0] = (f.x ^ l.x) & m;
+            x[i].v[1] = (f.y ^ l.y) & m;
+            x[i].v[2] = (f.z ^ l.z) & m;
+            x[i].v[3] = (f.w ^ l.w) & m;
+            n_ok += ok ? 1u : 0u;
+            bad |= present && !in_range;
         }
-        const uint4 f = id[(size_t)bi * w4 + lane];
-        const uint4 l = lv[(size_t)lj * w4 + lane];
-        U4 x;
-        x.v[0] = f.x ^ l.x;
-        x.v[1] = f.y ^ l.y;
-        x.v[2] = f.z ^ l.z;
-        x.v[3] = f.w ^ l.w;
-        add_bits<P>(c, x);
-        ++n_ok;
-    }
+        add_eight<P>(c, x);
+    };
+    int64_t p = a;
+    for (; p + 8 <= b; p += 8) group(p, false);
+    if (p < b) group(p, true);
+    if (bad && lane == 0) atomicOr(err, kErrRange);
     return at_least<P>(c, (n_ok + 1u) / 2u);
 }
 

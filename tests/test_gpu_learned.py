@@ -11,6 +11,8 @@ flips of the hidden layer. Tolerances:
   embeddings   |e_gpu - e_oracle| <= 1e-3 per element, row norm <= 5e-3
                (against the unrounded float64 oracle: row norm <= 3e-2)
   gradients    ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-2 per parameter
+               (against the unrounded float64 definition: <= 5.8e-2, the bf16
+               storage alone moving the oracle's gradients by up to 4.8%)
   scores       the shortlist scores the E4M3 scoring embeddings,
                round_e4m3(16 e) / 16 (mlp.scoring_embeddings); members of a
                shortlist score at least the oracle's k-th score minus 1e-2
@@ -107,6 +109,15 @@ def test_gradients_match_oracle(D, H, E, B):
     for k in ("W1", "b1", "W2", "b2"):
         rel = np.linalg.norm(g[k] - o_g[k]) / np.linalg.norm(o_g[k])
         assert rel <= 1e-2, (k, rel)
+    # Against the unrounded float64 definition: the bf16 storage of weights
+    # and hidden activations alone moves the oracle's own gradients by at
+    # most 4.8% (W1 at D = 2048; below 2.8% elsewhere, computed with the
+    # oracle on these inputs), so the GPU must be within 1e-2 + 4.8e-2 of it.
+    x_loss, x_g = mlp.loss_and_grads(_f64(p), mlp.bipolar(q, D), mlp.bipolar(r, D), TAU)
+    assert abs(loss - x_loss) <= 2e-3 * abs(x_loss) + 1e-4
+    for k in ("W1", "b1", "W2", "b2"):
+        rel = np.linalg.norm(g[k] - x_g[k]) / np.linalg.norm(x_g[k])
+        assert rel <= 5.8e-2, (k, rel)
     m.close()
     ctx.close()
 
