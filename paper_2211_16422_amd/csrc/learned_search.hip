@@ -489,7 +489,13 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     const int64_t c0 = max(r0, tile_lo[tile]);
     const int64_t c1 = min(r0 + kCollectChunk, tile_hi[tile]);
     if (c0 >= c1) return;
-    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w & 3, wn = w >> 2;
+    // the chunk's end row in a scalar register (32-bit: the library has
+    // fewer than 2^31 rows)
+    const uint32_t e1 = __builtin_amdgcn_readfirstlane((uint32_t)c1);
+    // the wave index in a scalar register: everything derived from it is
+    // wave-uniform scalar work
+    const int t = threadIdx.x, l = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = w & 3, wn = w >> 2;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
     // This pass's absolute 128-row blocks meeting [c0, c1): pass 0 the
     // multiples of kPassStride, pass 1 the others. Rows of a block below c0
@@ -511,6 +517,12 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         return g % kPassStride == 0 ? g + 1 : g;
     };
     uint32_t g_issue = first, g_epi = first;
+    // the pass's last block in the chunk: the loads issued for block steps
+    // past the end re-read it into a buffer that is never scored, so that
+    // every step waits for the same number of loads, with no branch
+    const uint32_t g_last =
+        pass == 0 ? (uint32_t)(f0 + (n0 - 1) * kPassStride)
+                  : (uint32_t)((g_hi - 1) % kPassStride == 0 ? g_hi - 2 : g_hi - 1);
 
     // rows [128 g, + 128) of the block g_issue points to into sA[b % kBufs]:
     // load x of wave w fills bytes [1024 (NL w + x), + 1024) of the buffer
@@ -518,11 +530,11 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // of row R = o / E, o the byte offset of the lane, with the row's piece
     // (slot ^ swz(R)); rows past c1 repeat the last row
     auto issue = [&](int b) {  // block b, the one g_issue points to
-        const int64_t mb = (int64_t)g_issue * 128;
+        const uint32_t mb = (b < nblk ? g_issue : g_last) * 128u;
         g_issue = next_block(g_issue);
         const uint32_t base = (uint32_t)(uintptr_t)&sA[b % kBufs][0];
         const uint8_t* gbase = lib_emb8 + (size_t)mb * E;  // wave-uniform
-        const int last = (int)min((int64_t)127, c1 - 1 - mb);
+        const int last = (int)min(127u, e1 - 1u - mb);
 #pragma unroll
         for (int x = 0; x < NL; ++x) {
             const int ci = w * NL + x;
@@ -580,12 +592,38 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             for (int c = 0; c < 2; ++c)
                 aoff[kk][c] = (uint32_t)(R * E + 16 * ((4 * kk + 2 * (l >> 5) + c) ^ sw));
     }
-    const uint32_t e1 = (uint32_t)c1;
+    // rows [wlo, whi) lie inside the chunk and inside the window of every
+    // query of the wave (wave-uniform): a block whose 32 rows of the wave
+    // fall in it needs no per-row window test
+    uint32_t wlo, whi;
+    {
+        uint32_t lo_all = 0, hi_all = e1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (qok[j]) {
+                lo_all = max(lo_all, qlo[j]);
+                hi_all = min(hi_all, qhi[j]);
+            }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo_all = max(lo_all, (uint32_t)__shfl_xor((int)lo_all, o));
+            hi_all = min(hi_all, (uint32_t)__shfl_xor((int)hi_all, o));
+        }
+        wlo = __builtin_amdgcn_readfirstlane(lo_all);
+        whi = __builtin_amdgcn_readfirstlane(hi_all);
+    }
     // The B operands are in registers before the pipeline starts, so that no
     // wait for them is left inside the loop, where it would also wait for the
-    // prefetched blocks (vmcnt counts in issue order).
+    // prefetched blocks (vmcnt counts in issue order). The empty asm
+    // statements consume the loaded values here, so the compiler can neither
+    // sink the loads below the prefetch (the restrict-qualified query rows
+    // would let it) nor leave their wait to the loop.
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) asm volatile("" : "+v"(bq[j][kk]));
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-    for (int b = 0; b < kBufs - 1 && b < nblk; ++b) issue(b);
+    for (int b = 0; b < kBufs - 1; ++b) issue(b);
 
     // the wave's LDS hit list and its flush to the per-query global buffers
     uint32_t wcount = 0;  // wave-uniform
@@ -653,17 +691,14 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             bool hit[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) hit[j] = __ballot(max16(a[j]) >= qthr[j]) != 0;
-            if (hit[0] || hit[1]) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!hit[j]) continue;  // one test per tile, not per position
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const uint32_t g = gl + roff(r);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        if (!hit[j]) continue;
-                        const float sc = a[j][r];
-                        const uint64_t m = __ballot(sc >= qthr[j]);
-                        if (m != 0) append(m, sc >= qthr[j], sc, g, j);
-                    }
+                    const float sc = a[j][r];
+                    const uint64_t m = __ballot(sc >= qthr[j]);
+                    if (m != 0) append(m, sc >= qthr[j], sc, gl + roff(r), j);
                 }
             }
         } else {  // window or chunk edge inside the wave's rows: per-row masks
@@ -684,25 +719,16 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         const uint32_t wb = g_epi * 128 + wr * 32;
         g_epi = next_block(g_epi);
         gl = wb + 4u * (uint32_t)(l >> 5);
-        bool inside = wb + 32 <= e1;
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            inside = inside && (!qok[j] || (wb >= qlo[j] && wb + 32 <= qhi[j]));
-        fast = __ballot(!inside) == 0;
+        fast = wb >= wlo && wb + 32 <= whi;
     };
-    // Block b has landed (the loads of up to kBufs - 2 later blocks may stay
-    // in flight); after the barrier every wave is done with block b - 1, whose
-    // buffer takes block b + kBufs - 1. One barrier per block.
+    // Block b has landed (the loads of the kBufs - 2 later steps stay in
+    // flight: loads complete in issue order); after the barrier every wave is
+    // done with block b - 1, whose buffer takes step b + kBufs - 1. One
+    // barrier per block.
     auto wait_block = [&](int b) {
-        static_assert(kBufs == 4, "one wait per number of blocks ahead");
-        if (b + 2 < nblk)
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * NL));
-        else if (b + 1 < nblk)
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(NL));
-        else
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm((kBufs - 2) * NL));
         __syncthreads();
-        if (b + kBufs - 1 < nblk) issue(b + kBufs - 1);
+        issue(b + kBufs - 1);
     };
     // block b's matrix instructions: every A operand read first, then the
     // E / 64 steps of both query tiles
@@ -716,6 +742,10 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             av[kk] = v8i32{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
                            (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
         }
+        // all LDS reads in flight before the first matrix instruction (the
+        // scheduler would otherwise interleave them to save registers and
+        // expose the LDS latency once per step)
+        __builtin_amdgcn_sched_barrier(0);
         a[0] = a[1] = f32x16{0};
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
@@ -750,6 +780,8 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     else
         examine(accB, glB, fastB);
     flush();
+    // the re-reads issued past the end land before the LDS is released
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
 }
 
 // One workgroup per query of the pass: the k largest keys of its buffer, in
