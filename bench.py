@@ -583,7 +583,7 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
         model.embed_library()
         idx, dist, fb = model.search(q_hv, q_pmz, q_ch, k)
         agree = float(((idx == e_idx) & (dist == e_dist))[has].float().mean().item())
-        fbr = float(fb.float().mean().item())
+        fbr = float((fb != 0).float().mean().item())
         log(f"learned {tag}: top-1 agreement {agree:.5f}, fallback {fbr:.5f}")
         return agree, fbr
 
@@ -638,6 +638,9 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
         "top1_agreement_training_free_sketch": agree_sketch,
         "top1_agreement_training_free_sketch_uncentred": agree_sketch0, "fallback_rate": fbr,
         "fallback_rate_sketch": fb_sketch,
+        "fallback_reasons": {r: int((fb == c).sum().item()) for c, r in
+                             ((1, "buffer_overflow"), (2, "too_few_kept"),
+                              (3, "kth_below_threshold"))},
         "exhaustive_s_warm_median": ex, "speedup_vs_popcount": ex["popcount"] / step_s,
         "speedup_vs_mfma_fp8": ex["mfma_fp8"] / step_s,
         "speedup_vs_mfma_fp4": ex["mfma_fp4"] / step_s,
@@ -678,7 +681,7 @@ def finish_learned(line, state, sample, side, o_idx, o_dist, o_qhv, t, desc):
                                      "oracle exhaustive top-1 (the judge) of " + desc, t)
     line["parity_sample"] = {"queries": int(len(sample)), "sampling": f"random, seed {SAMPLE_SEED}",
                              "top1_agreement_vs_oracle": agree,
-                             "fallback_in_sample": int(fb.sum()),
+                             "fallback_in_sample": int((fb != 0).sum()),
                              "rescored_distances_exact": exact}
     log(f"learned sample: agreement with the oracle {agree:.4f}, rescoring exact: {exact}")
 

@@ -538,11 +538,11 @@ homs_status homs_model_library_embeddings(homs_model *model, uint8_t *d_out_fp8,
  * them (lowest library index among equal distances; -1 / -1 without
  * candidates). Candidates are found with score thresholds (one estimated
  * from a sample of the window, then one refined from the hits in every
- * eighth 128-row block of the sorted library). d_out_fallback[q] = 1 marks a
- * query whose shortlist could not be formed this way (its candidate buffer
- * overflowed, a threshold kept fewer than min(k, window) candidates, or the
- * k-th kept candidate scores below the refined threshold); its result is the
- * exhaustive window search. d_out_shortlist (optional, [nq][k] int64) receives each query's
+ * eighth 128-row block of the sorted library). d_out_fallback[q] != 0 marks
+ * a query whose shortlist could not be formed this way, with the reason: 1
+ * its candidate buffer overflowed, 2 a threshold kept fewer than
+ * min(k, window) candidates, 3 the k-th kept candidate scores below the
+ * refined threshold; its result is the exhaustive window search. d_out_shortlist (optional, [nq][k] int64) receives each query's
  * shortlist by descending score, -1 past the window's size and for fallback
  * queries. Same query arguments as homs_search_window. The model's embed size
  * must be 64, 128 or 256 (HOMS_E_UNSUPPORTED otherwise). Asynchronous; grows

@@ -37,6 +37,7 @@
 //  5. fallback: the flagged queries are listed on the device and their whole
 //     windows scanned, one wave per 512-row unit, into the same keys.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "gemm_bf16.h"
@@ -268,12 +269,12 @@ __device__ RadixDigit radix_digit(const uint32_t* hist, uint32_t r)
 
 // One workgroup per query of the pass: the r-th largest of its in-window
 // sample scores (radix select over order-preserving keys, 8 bits per round),
-// with r chosen so that about kCapacity / 4 window candidates are expected
-// at or above it; -inf keeps the whole window.
+// with r chosen so that about `target` window candidates are expected at or
+// above it; -inf keeps the whole window.
 __global__ __launch_bounds__(kThreads) void threshold_kernel(
-    int64_t q_begin, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
-    const int64_t* __restrict__ hi, const SampleGrid* __restrict__ grids,
-    const float* __restrict__ S, float* __restrict__ thr)
+    int64_t q_begin, int64_t target, const uint32_t* __restrict__ qperm,
+    const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
+    const SampleGrid* __restrict__ grids, const float* __restrict__ S, float* __restrict__ thr)
 {
     __shared__ uint32_t hist[256];
     __shared__ RadixDigit s_rd;
@@ -294,7 +295,6 @@ __global__ __launch_bounds__(kThreads) void threshold_kernel(
         return;
     }
     const float* v = S + (size_t)qp * kSample + i0;
-    const int64_t target = kCapacity / 4;
     int64_t r64 = (target * ns + w - 1) / w;
     uint32_t r = (uint32_t)(r64 < 1 ? 1 : (r64 > ns ? ns : r64));
     // the sample keys stay in registers for the four rounds
@@ -344,12 +344,13 @@ __host__ __device__ inline int64_t pass0_rows_below(int64_t x)
 // One workgroup per query of the pass: the refined threshold. Pass 0 kept,
 // from its 1 / kPassStride share of the window, every candidate scoring at
 // or above the sampled threshold; the r-th largest of them, r = ceil(target x
-// share / window) with target = 4 max(k, 64) (about that many window
-// candidates are then expected at or above it), is the threshold of pass 1.
-// Windows kept whole (-inf), a pass-0 buffer that overflowed, or fewer than r
-// pass-0 candidates keep the sampled threshold.
+// share / window) (about `target` window candidates are then expected at or
+// above it), is the threshold of pass 1. Windows kept whole (-inf), a pass-0
+// buffer that overflowed, or fewer than r pass-0 candidates keep the sampled
+// threshold.
 __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
-    int64_t q_begin, int k, const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
+    int64_t q_begin, int64_t target, const uint32_t* __restrict__ qperm,
+    const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const uint32_t* __restrict__ count,
     const uint64_t* __restrict__ buf, const float* __restrict__ thr, float* __restrict__ thr2)
 {
@@ -362,7 +363,6 @@ __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
     const int64_t a = lo[qi], b = hi[qi], w = b - a;
     const uint32_t cnt = count[qp * kCountStride];
     const int64_t share = pass0_rows_below(b) - pass0_rows_below(a);
-    const int64_t target = 4 * (int64_t)max(k, 64);
     const int64_t r64 = w > 0 ? (target * share + w - 1) / w : 0;
     // uniform
     if (t1 == -INFINITY || cnt > (uint32_t)kCapacity || r64 < 1 || (int64_t)cnt < r64) {
@@ -811,7 +811,10 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     const int n = (int)min(cnt, (uint32_t)kCapacity);
     const int need = (int)min((int64_t)k, w);
     const bool sampled = thr[p] != -INFINITY;
-    bool bad = cnt > (uint32_t)kCapacity || (sampled && n < need);
+    // fallback reason: 1 the buffer overflowed, 2 fewer than min(k, window)
+    // candidates were kept, 3 the k-th kept scores below the threshold
+    uint8_t why = cnt > (uint32_t)kCapacity ? 1 : (sampled && n < need) ? 2 : 0;
+    bool bad = why != 0;
     const uint64_t* keys = buf + (size_t)blockIdx.x * kCapacity;
     const int kk = min(k, n);  // keys kept
     // The scoring kernel stored (score << 32 | sorted row); the result keys
@@ -904,12 +907,15 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
         // Every window candidate scoring at or above thr is in the buffer
         // (pass 1 kept those, pass 0 kept more of its blocks); the kk kept
         // keys are the window's best only if the kk-th scores at least thr.
-        if (sampled && (uint32_t)(s_sel[kk - 1] >> 32) < fkey(thr[p])) bad = true;
+        if (sampled && (uint32_t)(s_sel[kk - 1] >> 32) < fkey(thr[p])) {
+            bad = true;
+            why = 3;
+        }
     }
     int64_t* out = shortlist + (size_t)qi * k;
     for (int i = threadIdx.x; i < k; i += blockDim.x)
         out[i] = (!bad && i < kk) ? (int64_t)(0xFFFFFFFFu - (uint32_t)s_sel[i]) : -1;
-    if (threadIdx.x == 0) fallback[qi] = bad ? 1 : 0;
+    if (threadIdx.x == 0) fallback[qi] = why;
 }
 
 // one wave per query: exact distances of the shortlist, minimum merged
@@ -1006,6 +1012,23 @@ __global__ void zero_u32_kernel(int64_t n, uint32_t* __restrict__ p)
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Window candidates expected at or above each threshold for shortlists of k.
+// Pass 1's target t2 leaves k a margin of four standard deviations of the
+// count estimated from the r = t2 / kPassStride best pass-0 hits (relative
+// spread about 1 / sqrt(r)): the smallest t2 with t2 - 4 sqrt(8 t2) >= k, and
+// at least 256. The sampled threshold targets eight times that, between
+// kCapacity / 4 and kCapacity / 2: on the widest windows the sample holds
+// only a few rows per candidate above the threshold (r of 4 at 2,048 of 2.5M
+// rows), and pass 0 must still find the r hits the refinement needs and,
+// where it does not, keep at least k candidates itself.
+void shortlist_targets(int k, int64_t* t1, int64_t* t2)
+{
+    const double c = 4.0 * std::sqrt((double)kPassStride);
+    const double x = 0.5 * (c + std::sqrt(c * c + 4.0 * (double)k));
+    *t2 = std::max<int64_t>(256, (int64_t)std::ceil(x * x));
+    *t1 = std::min<int64_t>(kCapacity / 2, std::max<int64_t>(kCapacity / 4, 8 * *t2));
+}
+
 }  // namespace
 
 int learned_max_k() { return kMaxK; }
@@ -1066,6 +1089,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
     if (e != hipSuccess) return e;
     const int64_t max_chunks = (c->lib.n + kCollectChunk - 1) / kCollectChunk;
     if (max_chunks > 65535) return hipErrorInvalidConfiguration;
+    int64_t t1, t2;
+    shortlist_targets(k, &t1, &t2);
     for (int64_t b0 = 0; b0 < nq; b0 += plan.batch) {
         const int64_t b1 = std::min(nq, b0 + plan.batch), nb = b1 - b0;
         const int64_t tiles = (nb + kTileQ - 1) / kTileQ;
@@ -1073,7 +1098,7 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         if (e != hipSuccess) return e;
         sample_scores_kernel<<<(uint32_t)(tiles * kSampleSplit), 256, 0, s>>>(
             E, b0, b1, q_sorted, tlo, thi, m->lib_emb, grids, S);
-        threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, qperm, lo, hi, grids, S, thr);
+        threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, t1, qperm, lo, hi, grids, S, thr);
         zero_u32_kernel<<<blocks_for(nb * kCountStride), kThreads, 0, s>>>(nb * kCountStride,
                                                                            count);
         hipEvent_t ea = hook.mark ? hook.mark(hook.user, s) : nullptr;
@@ -1099,8 +1124,8 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         // pass 0 with the sampled threshold, the refined threshold from its
         // hits, pass 1 with the refined one (same buffers, appended)
         collect(std::integral_constant<int, 0>{}, thr);
-        refine_threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, qperm, lo, hi, count, buf,
-                                                                  thr, thr2);
+        refine_threshold_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, t2, qperm, lo, hi, count,
+                                                                  buf, thr, thr2);
         collect(std::integral_constant<int, 1>{}, thr2);
         if (hook.mark && ea) hook.span(hook.user, ea, hook.mark(hook.user, s));
         select_kernel<<<(uint32_t)nb, kThreads, 0, s>>>(b0, k, count, buf, thr2, qperm, lo, hi,
