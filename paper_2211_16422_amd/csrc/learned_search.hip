@@ -416,9 +416,10 @@ __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
 // stream through four LDS buffers filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4, no staging registers): one load moves 1 KB (64
 // lanes x 16 bytes) of a block's rows, so a 128-row block of E-byte rows
-// takes E / 64 loads per wave. Three blocks are in flight while one is
-// scored, and one barrier per block both publishes the landed block and
-// frees the buffer of the block before it. The 16-byte piece
+// takes E / 64 loads per wave. Per block step, the block's A operands are in
+// registers (read from LDS one step ahead), the next block waits in LDS and
+// two more are in flight; one barrier per block both publishes the landed
+// block and frees the buffer of the block in registers. The 16-byte piece
 // p of row R sits at slot p ^ swz(R) of the row, swz(R) = (R / (16 / P)) mod
 // P with P = E / 16 pieces per row, so the 16 rows a quarter-wave reads
 // together land on 16 distinct 16-byte bank groups. The loads are issued
@@ -426,22 +427,25 @@ __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
 // drain every outstanding LDS load before any LDS read and cap the prefetch
 // at one block.
 //
-// Epilogue, software-pipelined: two accumulator sets are used in turn, and
-// the scores of block b - 1 are examined right after block b's matrix
-// instructions are issued, so that the compares and ballots run while the
-// matrix core works (the waves leave each barrier together, so no other
-// wave would cover an epilogue placed before them). When the wave's 32 rows of
-// the block lie inside every window of its queries (the usual case), one
-// ballot per query tile on each lane's largest score first tells whether the
-// tile has any hit; only such tiles take a compare and a ballot per position
-// (skipped unless some lane hits). Otherwise the block's positions are masked
-// row by row after the matrix instructions. Hits go to the wave's own LDS list at positions
-// counted from the ballot (no atomics, no global loads), flushed to the
-// per-query global buffers when half full and at the end.
+// Epilogue, software-pipelined: two accumulator sets are used in turn. The
+// straight-line part of a step's other work (the hit pre-check of block
+// b - 1, the next loads, the next block's LDS reads, bookkeeping) is placed
+// between block b's matrix instructions, where the wave issues it while the
+// matrix core runs; the hits of block b - 1 follow the matrix instructions.
+// When the wave's 32 rows of the block lie inside every window of its
+// queries (the usual case), one ballot per query tile on each lane's largest
+// score first tells whether the tile has any hit; only such tiles take a
+// compare and a ballot per position (skipped unless some lane hits).
+// Otherwise the block's positions are masked row by row. Hits go to the
+// wave's own LDS list at positions counted from the ballot (no atomics, no
+// global loads), flushed to the per-query global buffers when half full and
+// at the end.
 constexpr int kWaveList = 384;  // LDS entries per wave
 
 // s_waitcnt immediate: vmcnt(n), expcnt and lgkmcnt left at their maxima
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
+// vmcnt(n) and lgkmcnt(0)
+constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70; }
 
 typedef int v8i32 __attribute__((ext_vector_type(8)));
 
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) asm volatile("" : "+v"(bq[j][kk]));
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-    for (int b = 0; b < kBufs - 1; ++b) issue(b);
+    for (int b = 0; b < kBufs; ++b) issue(b);
 
     // the wave's LDS hit list and its flush to the per-query global buffers
     uint32_t wcount = 0;  // wave-uniform
@@ -680,20 +684,24 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // wb + i with wb = the block's first row + 32 wr: gl + roff(r) with
     // gl = wb + 4 (l / 32).
     auto roff = [](int r) -> uint32_t { return (uint32_t)(8 * (r >> 2) + (r & 3)); };
-    // The scores of a scored block, examined while the next block's matrix
-    // instructions run: gl = the row of accumulator register 0 in this lane,
-    // fast = every row of the wave lies inside every window of its queries.
-    auto examine = [&](const f32x16(&a)[2], uint32_t gl, bool fast) {
-        if (fast) {
-            // which query tiles have a hit at all: the largest of a lane's 16
-            // scores (one query, 16 rows) against its threshold, one ballot
-            // per tile; only those take a compare and a ballot per position
-            bool hit[2];
+    // The scores of a scored block are examined while the next block's
+    // matrix instructions run: gl = the row of accumulator register 0 in this
+    // lane, fast = every row of the wave lies inside every window of its
+    // queries. The pre-check (fast case): which query tiles have a hit at
+    // all, from the largest of each lane's 16 scores (one query, 16 rows)
+    // against its threshold, one ballot per tile; straight-line code, so it
+    // can sit between matrix instructions.
+    auto precheck = [&](const f32x16(&a)[2], uint64_t (&hit)[2]) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) hit[j] = __ballot(max16(a[j]) >= qthr[j]) != 0;
+        for (int j = 0; j < 2; ++j) hit[j] = __ballot(max16(a[j]) >= qthr[j]);
+    };
+    // the hits themselves: in the fast case a compare and a ballot per
+    // position of the tiles the pre-check flagged, else per-row masks
+    auto examine = [&](const f32x16(&a)[2], uint32_t gl, bool fast, const uint64_t (&hit)[2]) {
+        if (fast) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (!hit[j]) continue;  // one test per tile, not per position
+                if (hit[j] == 0) continue;  // one test per tile, not per position
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const float sc = a[j][r];
@@ -721,20 +729,9 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         gl = wb + 4u * (uint32_t)(l >> 5);
         fast = wb >= wlo && wb + 32 <= whi;
     };
-    // Block b has landed (the loads of the kBufs - 2 later steps stay in
-    // flight: loads complete in issue order); after the barrier every wave is
-    // done with block b - 1, whose buffer takes step b + kBufs - 1. One
-    // barrier per block.
-    auto wait_block = [&](int b) {
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm((kBufs - 2) * NL));
-        __syncthreads();
-        issue(b + kBufs - 1);
-    };
-    // block b's matrix instructions: every A operand read first, then the
-    // E / 64 steps of both query tiles
-    auto score = [&](int b, f32x16(&a)[2]) {
+    // block b's A operands (this lane's row, all E / 64 steps) from LDS
+    auto read_a = [&](int b, v8i32(&av)[KS]) {
         const uint8_t* Ab = sA[b % kBufs];
-        v8i32 av[KS];
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
             const uint4 u0 = *(const uint4*)(Ab + aoff[kk][0]);
@@ -742,43 +739,81 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
             av[kk] = v8i32{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
                            (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
         }
-        // all LDS reads in flight before the first matrix instruction (the
-        // scheduler would otherwise interleave them to save registers and
-        // expose the LDS latency once per step)
-        __builtin_amdgcn_sched_barrier(0);
-        a[0] = a[1] = f32x16{0};
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-            a[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[kk], bq[0][kk], a[0], 0, 0,
-                                                                   0, 0, 0, 0);
-            a[1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[kk], bq[1][kk], a[1], 0, 0,
-                                                                   0, 0, 0, 0);
-        }
     };
 
-    // Two accumulator sets in turn: block b scores into one while block
-    // b - 1's scores, in the other, are examined.
+    // Software pipeline, one step per block b: block b's A operands are in
+    // registers (read from LDS during step b - 1), block b + 1 sits in LDS,
+    // blocks b + 2 and b + 3 are in flight. Step b waits for block b + 1 (own
+    // loads, then the barrier for everyone's; the barrier also means every
+    // wave has its block-b operands, so block b's buffer is free), issues the
+    // loads of block b + 4 into that buffer and runs block b's matrix
+    // instructions with the rest of the step's work placed between them:
+    // the pre-check of block b - 1, the loads, the LDS reads of block b + 1
+    // and the block bookkeeping. A wave keeps issuing while its matrix
+    // instruction runs, so that work is hidden behind the matrix core; the
+    // scheduling barriers keep the compiler from regrouping it. The hits of
+    // block b - 1 (branches, rare) follow the matrix instructions. Two
+    // accumulator and two operand sets are used in turn.
+    auto step = [&](int b, f32x16(&cur)[2], const f32x16(&prev)[2], const v8i32(&avc)[KS],
+                    v8i32(&avn)[KS], uint32_t glp, bool fastp, uint32_t& glc, bool& fastc) {
+        // this wave's LDS reads of block b are complete before the barrier,
+        // so no wave can refill block b's buffer under them
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((kBufs - 2) * NL));
+        __syncthreads();
+        uint64_t hit[2];
+        // work item t runs after matrix instruction min(at[t], 2 KS - 1); the
+        // LDS reads of block b + 1 come late, when most of block b's operand
+        // registers are free again
+        constexpr int at[5] = {0, 1, 2, 3, 5};
+        auto work = [&](int t) {
+            if (t == 0) hit[0] = __ballot(max16(prev[0]) >= qthr[0]);
+            if (t == 1) hit[1] = __ballot(max16(prev[1]) >= qthr[1]);
+            if (t == 2) issue(b + kBufs);
+            if (t == 3) block_info(glc, fastc);
+            if (t == 4) read_a(b + 1, avn);
+        };
+        constexpr int kWork = 5;
+#pragma unroll
+        for (int i = 0; i < 2 * KS; ++i) {
+            const int kk = i >> 1, j = i & 1;
+            cur[j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                avc[kk], bq[j][kk], kk == 0 ? f32x16{0} : cur[j], 0, 0, 0, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kWork; ++t)
+                if (min(at[t], 2 * KS - 1) == i) {
+                    work(t);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        }
+        if (b > 0) examine(prev, glp, fastp, hit);
+        if (wcount > kWaveList / 2) flush();  // wave-uniform
+    };
+
     f32x16 accA[2], accB[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) accA[j] = accB[j] = f32x16{0};
+    v8i32 avA[KS], avB[KS];
     uint32_t glA = 0, glB = 0;
     bool fastA = false, fastB = false;
+    // block 0 landed (the loads of blocks 1 .. kBufs - 1 stay in flight)
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm((kBufs - 1) * NL));
+    __syncthreads();
+    read_a(0, avA);
     for (int b = 0; b < nblk; b += 2) {
-        wait_block(b);
-        score(b, accA);
-        if (b > 0) examine(accB, glB, fastB);
-        block_info(glA, fastA);
-        if (wcount > kWaveList / 2) flush();  // wave-uniform
-        if (b + 1 < nblk) {
-            wait_block(b + 1);
-            score(b + 1, accB);
-            examine(accA, glA, fastA);
-            block_info(glB, fastB);
-            if (wcount > kWaveList / 2) flush();
+        step(b, accA, accB, avA, avB, glB, fastB, glA, fastA);
+        if (b + 1 < nblk) step(b + 1, accB, accA, avB, avA, glA, fastA, glB, fastB);
+    }
+    {  // the last block's hits
+        uint64_t hit[2];
+        if (nblk & 1) {
+            precheck(accA, hit);
+            examine(accA, glA, fastA, hit);
+        } else {
+            precheck(accB, hit);
+            examine(accB, glB, fastB, hit);
         }
     }
-    if (nblk & 1)
-        examine(accA, glA, fastA);
-    else
-        examine(accB, glB, fastB);
     flush();
     // the re-reads issued past the end land before the LDS is released
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
