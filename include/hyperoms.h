@@ -44,6 +44,15 @@ typedef int32_t homs_status;
 #define HOMS_E_STATE (-4)       /* call not valid in the context's state */
 #define HOMS_E_UNSUPPORTED (-5) /* valid request this library version does not handle */
 
+/*
+ * Test hook: with the environment variable HOMS_TEST_FAIL_ALLOC=n, the n-th
+ * device allocation of the library after the variable last changed value
+ * fails without allocating, and the call that made it returns HOMS_E_OOM
+ * (text after the number, as in "3:b", only re-arms the count). An
+ * allocation failure leaves the context usable; unset, the variable costs
+ * one getenv per allocation.
+ */
+
 typedef struct homs_ctx homs_ctx;
 
 /*

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -14,6 +15,30 @@
 #include "learned.h"
 #include "persist.h"
 #include "preprocess.h"
+
+namespace homs {
+
+hipError_t dev_malloc(void** p, size_t bytes)
+{
+    const char* v = std::getenv("HOMS_TEST_FAIL_ALLOC");
+    if (v && *v) {
+        static std::mutex mu;
+        static std::string armed;
+        static long calls = 0;
+        std::lock_guard<std::mutex> lock(mu);
+        if (armed != v) {
+            armed = v;
+            calls = 0;
+        }
+        if (++calls == std::strtol(v, nullptr, 10)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
+
+}  // namespace homs
 
 namespace {
 
@@ -155,7 +180,7 @@ homs_status ensure_workspace(homs_ctx* c, size_t bytes, hipStream_t s)
     if (c->ws.ptr) (void)hipFree(c->ws.ptr);
     c->ws = homs::Workspace{};
     const size_t want = bytes + bytes / 4;
-    HIP_TRY(c, hipMalloc(&c->ws.ptr, want), "hipMalloc(workspace)");
+    HIP_TRY(c, homs::dev_malloc(&c->ws.ptr, want), "hipMalloc(workspace)");
     c->ws.bytes = want;
     return HOMS_OK;
 }
@@ -370,9 +395,9 @@ homs_status homs_create(const homs_params* p, int32_t device, homs_ctx** out)
     }
     homs::generate_codebook(p->dim, (uint32_t)c->n_bins, p->n_levels, c->p.id_flips, p->seed,
                             p->encoding, id.data(), lv.data());
-    hipError_t e = hipMalloc(&c->d_id, id.size() * 4);
-    if (e == hipSuccess) e = hipMalloc(&c->d_level, lv.size() * 4);
-    if (e == hipSuccess) e = hipMalloc(&c->d_err, 256);
+    hipError_t e = homs::dev_malloc(&c->d_id, id.size() * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&c->d_level, lv.size() * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&c->d_err, 256);
     if (e == hipSuccess) e = hipMemcpy(c->d_id, id.data(), id.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_level, lv.data(), lv.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->d_err, 0, 256);
@@ -493,15 +518,15 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     L.n = n;
     const size_t tmp_bytes = homs::library_sort_temp_bytes(n);
     void* tmp = nullptr;
-    hipError_t e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
-    if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
-    if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
+    hipError_t e = homs::dev_malloc(&L.hv, (size_t)n * c->words * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&L.pmz, (size_t)n * 8);
+    if (e == hipSuccess) e = homs::dev_malloc(&L.charge, (size_t)n);
     // the MFMA epilogue reads library indices in groups past the last row
     const size_t orig_pad = (size_t)homs::search_mfma_row_pad();
-    if (e == hipSuccess) e = hipMalloc(&L.orig, ((size_t)n + orig_pad) * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&L.orig, ((size_t)n + orig_pad) * 4);
     if (e == hipSuccess) e = hipMemsetAsync(L.orig + n, 0, orig_pad * 4, s);
-    if (e == hipSuccess) e = hipMalloc(&L.slot, (size_t)n * 4);
-    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
+    if (e == hipSuccess) e = homs::dev_malloc(&L.slot, (size_t)n * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&tmp, tmp_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
     hipEvent_t e0 = e == hipSuccess ? prof_mark(c, s) : nullptr;
     if (e == hipSuccess)
@@ -1244,7 +1269,7 @@ homs_status homs_model_gradients(homs_model* m, int32_t batch, const uint32_t* d
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     float* d_loss = nullptr;
-    HIP_TRY(c, hipMalloc(&d_loss, 256), "hipMalloc(loss)");
+    HIP_TRY(c, homs::dev_malloc(&d_loss, 256), "hipMalloc(loss)");
     hipError_t e = homs::model_step(m, batch, d_q_hv, d_r_hv, tau, 0.f, false, d_loss, s);
     float loss = 0.f;
     if (e == hipSuccess) e = hipMemcpyAsync(&loss, d_loss, 4, hipMemcpyDeviceToHost, s);
@@ -1343,8 +1368,10 @@ homs_status homs_model_embed_library(homs_model* m, void* stream)
         m->lib_emb8 = nullptr;
         m->lib_emb_n = 0;
         const size_t rows = (size_t)std::max<int64_t>(n, 1);
-        HIP_TRY(c, hipMalloc(&m->lib_emb, rows * m->E * 2), "hipMalloc(library embeddings)");
-        HIP_TRY(c, hipMalloc(&m->lib_emb8, rows * m->E), "hipMalloc(library embeddings)");
+        HIP_TRY(c, homs::dev_malloc(&m->lib_emb, rows * m->E * 2),
+                "hipMalloc(library embeddings)");
+        HIP_TRY(c, homs::dev_malloc(&m->lib_emb8, rows * m->E),
+                "hipMalloc(library embeddings)");
         m->lib_emb_n = n;
     }
     if (n > 0)
@@ -1655,11 +1682,11 @@ homs_status homs_library_load(homs_ctx* c, const char* path)
     const size_t orig_pad = (size_t)homs::search_mfma_row_pad();
     hipError_t e = hipSuccess;
     if (n > 0) {
-        e = hipMalloc(&L.hv, (size_t)n * c->words * 4);
-        if (e == hipSuccess) e = hipMalloc(&L.pmz, (size_t)n * 8);
-        if (e == hipSuccess) e = hipMalloc(&L.charge, (size_t)n);
-        if (e == hipSuccess) e = hipMalloc(&L.orig, ((size_t)n + orig_pad) * 4);
-        if (e == hipSuccess) e = hipMalloc(&L.slot, (size_t)n * 4);
+        e = homs::dev_malloc(&L.hv, (size_t)n * c->words * 4);
+        if (e == hipSuccess) e = homs::dev_malloc(&L.pmz, (size_t)n * 8);
+        if (e == hipSuccess) e = homs::dev_malloc(&L.charge, (size_t)n);
+        if (e == hipSuccess) e = homs::dev_malloc(&L.orig, ((size_t)n + orig_pad) * 4);
+        if (e == hipSuccess) e = homs::dev_malloc(&L.slot, (size_t)n * 4);
         if (e == hipSuccess) e = hipMemcpy(L.orig, orig.data(), (size_t)n * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(L.orig + n, 0, orig_pad * 4);
         if (e == hipSuccess) e = hipMemcpy(L.pmz, pmz.data(), (size_t)n * 8, hipMemcpyHostToDevice);

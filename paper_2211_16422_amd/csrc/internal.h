@@ -86,6 +86,18 @@ struct homs_ctx {
 
 namespace homs {
 
+// Every device allocation of the library: hipMalloc, except under the test
+// hook HOMS_TEST_FAIL_ALLOC=n (environment variable, read at every call):
+// the n-th call after the variable last changed value fails with
+// hipErrorOutOfMemory and allocates nothing (text after the number, as in
+// "3:b", only re-arms the count). api.hip.
+hipError_t dev_malloc(void** p, size_t bytes);
+template <class T>
+inline hipError_t dev_malloc(T** p, size_t bytes)
+{
+    return dev_malloc(reinterpret_cast<void**>(p), bytes);
+}
+
 // ---- kernel launchers (each in its own translation unit) -------------------
 
 // encode.hip

@@ -254,7 +254,7 @@ hipError_t model_alloc(homs_model* m)
     const size_t n1 = (size_t)m->H * m->D, n2 = (size_t)m->E * m->H;
     hipError_t e = hipSuccess;
     auto A = [&](void** p, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(p, bytes);
+        if (e == hipSuccess) e = dev_malloc(p, bytes);
         if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
     };
     A((void**)&m->W1, n1 * 4);
@@ -311,7 +311,7 @@ hipError_t model_embed(homs_model* m, int64_t n, const uint32_t* hv, float* out_
         if (m->emb_ws) (void)hipFree(m->emb_ws);
         m->emb_ws = nullptr;
         m->emb_ws_bytes = 0;
-        e = hipMalloc(&m->emb_ws, need);
+        e = dev_malloc(&m->emb_ws, need);
         if (e != hipSuccess) return e;
         m->emb_ws_bytes = need;
     }
@@ -370,7 +370,7 @@ hipError_t model_step(homs_model* m, int B, const uint32_t* q_hv, const uint32_t
         if (m->train_ws) (void)hipFree(m->train_ws);
         m->train_ws = nullptr;
         m->train_ws_bytes = 0;
-        e = hipMalloc(&m->train_ws, need);
+        e = dev_malloc(&m->train_ws, need);
         if (e != hipSuccess) return e;
         m->train_ws_bytes = need;
     }
@@ -545,7 +545,7 @@ hipError_t model_train(homs_model* m, int64_t n, const uint32_t* q_hv, const int
     const size_t sort_tmp = radix_sort_temp_bytes(cap);
     const size_t need = 2 * al((size_t)cap * 8) + 4 * al((size_t)cap * 4) + al(sort_tmp) + al(8);
     char* base = nullptr;
-    hipError_t e = hipMalloc((void**)&base, need);
+    hipError_t e = dev_malloc((void**)&base, need);
     if (e != hipSuccess) return e;
     char* p = base;
     auto take = [&](size_t bytes) {

@@ -52,7 +52,7 @@ extern "C" homs_status homs_measure_xor_popcount_rate(int32_t device, double* la
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) { st = HOMS_E_DEVICE; break; }
         const int blocks = prop.multiProcessorCount * 16;
         const int iters = 4096;
-        if (hipMalloc(&out, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) {
+        if (homs::dev_malloc(&out, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) {
             st = HOMS_E_OOM;
             break;
         }
