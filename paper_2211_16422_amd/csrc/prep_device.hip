@@ -21,6 +21,7 @@
 // an exclusive scan gives the CSR offsets, the second recomputes and writes.
 
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -219,8 +220,9 @@ __global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
     uint8_t* __restrict__ out_level)
 {
     __shared__ double s_mz[kWaves][kWaveCap], s_in[kWaves][kWaveCap];
+    __shared__ double s_tmz[kWaves][kWaveCap];
     __shared__ uint16_t s_pos[kWaves][kWaveCap], s_top[kWaves][kWaveCap],
-        s_ord[kWaves][kWaveCap];
+        s_ord[kWaves][kWaveCap], s_tpos[kWaves][kWaveCap];
     __shared__ int32_t s_bin[kWaves][kWaveCap];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     double* const smz = s_mz[w];
@@ -228,6 +230,8 @@ __global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
     uint16_t* const spos = s_pos[w];
     uint16_t* const stop = s_top[w];
     uint16_t* const sord = s_ord[w];
+    double* const tmz = s_tmz[w];
+    uint16_t* const tpos = s_tpos[w];
     int32_t* const sbin = s_bin[w];
     const int64_t stride = (int64_t)gridDim.x * kWaves;
     for (int64_t s = (int64_t)blockIdx.x * kWaves + w; s < n; s += stride) {
@@ -269,30 +273,69 @@ __global__ __launch_bounds__(64 * kWaves) void preprocess_wave_kernel(
         for (int e = l; e < m; e += 64) kept += !(sin_[e] < floor_i);
         for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o);
         const int k = kept < (int)pa.top_n ? kept : (int)pa.top_n;
-        for (int e = l; e < m; e += 64) {
-            const double ie = sin_[e], me = smz[e];
-            const uint32_t pe = spos[e];
-            if (ie < floor_i) continue;
-            int r = 0;
-            for (int j = 0; j < m; ++j) {
-                const double ij = sin_[j];
-                r += (!(ij < floor_i) && before_int(ij, smz[j], spos[j], ie, me, pe)) ? 1 : 0;
+        // one pass over the peaks ranks all of the lane's peaks at once
+        // (held in registers); peak j's fields are broadcast LDS reads, and
+        // the loop carries no dependence between iterations, so the reads of
+        // several iterations are in flight together
+        auto rank_top = [&](auto per_tag) {
+            constexpr int P = decltype(per_tag)::value;  // peaks per lane
+            double ie[P], me[P];
+            uint32_t pe[P];
+            int r[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int e = l + 64 * q < m ? l + 64 * q : m - 1;
+                ie[q] = sin_[e];
+                me[q] = smz[e];
+                pe[q] = spos[e];
+                r[q] = 0;
             }
-            if (r < k) stop[r] = (uint16_t)e;
+#pragma unroll 4
+            for (int j = 0; j < m; ++j) {
+                const double ij = sin_[j], mj = smz[j];
+                const uint32_t pj = spos[j];
+                const bool kj = !(ij < floor_i);
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    r[q] += (kj && before_int(ij, mj, pj, ie[q], me[q], pe[q])) ? 1 : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int e = l + 64 * q;
+                if (e < m && !(ie[q] < floor_i) && r[q] < k) stop[r[q]] = (uint16_t)e;
+            }
+        };
+        static_assert(kWaveCap == 256, "up to four peaks per lane");
+        if (m > 0) {  // wave-uniform
+            const int per = (m + 63) >> 6;
+            if (per == 1)
+                rank_top(std::integral_constant<int, 1>{});
+            else if (per == 2)
+                rank_top(std::integral_constant<int, 2>{});
+            else if (per == 3)
+                rank_top(std::integral_constant<int, 3>{});
+            else
+                rank_top(std::integral_constant<int, 4>{});
         }
         __builtin_amdgcn_wave_barrier();
-        // 4-5. the top-N in (m/z asc, position asc) order
+        // 4-5. the top-N in (m/z asc, position asc) order, ranked over a
+        // compact copy of their m/z and positions
         for (int t = l; t < k; t += 64) {
             const int e = stop[t];
-            const double me = smz[e];
-            const uint32_t pe = spos[e];
+            tmz[t] = smz[e];
+            tpos[t] = spos[e];
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int t = l; t < k; t += 64) {
+            const double me = tmz[t];
+            const uint32_t pe = tpos[t];
             int r = 0;
+#pragma unroll 4
             for (int u = 0; u < k; ++u) {
-                const int f = stop[u];
-                const double mf = smz[f];
-                r += (mf < me || (mf == me && spos[f] < pe)) ? 1 : 0;
+                const double mf = tmz[u];
+                r += (mf < me || (mf == me && (uint32_t)tpos[u] < pe)) ? 1 : 0;
             }
-            sord[r] = (uint16_t)e;
+            sord[r] = stop[t];
         }
         __builtin_amdgcn_wave_barrier();
         for (int t = l; t < k; t += 64) {
