@@ -65,7 +65,7 @@ ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
 MFMA_ENGINES = {"mfma_fp8": ("fp8 e4m3", MFMA_PEAK_TOPS, "mfma_direct_kernel<0> (fp8 e4m3)",
                              "fp8e4m3(+-1)->f32"),
                 "mfma_fp4": ("fp4 e2m1", MFMA_F4_PEAK_TOPS, "mfma_direct_kernel<4> (fp4 e2m1)",
-                             "fp4e2m1(+-1)->f32"),
+                             "fp4e2m1->f32"),
                 "mfma_int8": ("int8", MFMA_PEAK_TOPS, "mfma_direct_kernel<8> (int8 +-64)",
                               "i8(+-64)->i32")}
 

@@ -166,6 +166,7 @@ void free_library(homs::Library& L)
     if (L.charge) (void)hipFree(L.charge);
     if (L.orig) (void)hipFree(L.orig);
     if (L.slot) (void)hipFree(L.slot);
+    if (L.rowk) (void)hipFree(L.rowk);
     L = homs::Library{};
 }
 
@@ -526,6 +527,7 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     if (e == hipSuccess) e = homs::dev_malloc(&L.orig, ((size_t)n + orig_pad) * 4);
     if (e == hipSuccess) e = hipMemsetAsync(L.orig + n, 0, orig_pad * 4, s);
     if (e == hipSuccess) e = homs::dev_malloc(&L.slot, (size_t)n * 4);
+    if (e == hipSuccess) e = homs::dev_malloc(&L.rowk, ((size_t)n + orig_pad) * 4);
     if (e == hipSuccess) e = homs::dev_malloc(&tmp, tmp_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4, s);
     hipEvent_t e0 = e == hipSuccess ? prof_mark(c, s) : nullptr;
@@ -535,6 +537,7 @@ homs_status homs_encode_library(homs_ctx* c, int64_t n, const int64_t* d_offsets
     hipEvent_t e1 = e == hipSuccess ? prof_mark(c, s) : nullptr;
     if (e == hipSuccess) e = homs::launch_encode(c, n, d_offsets, d_bin, d_level, L.slot, L.hv, s);
     hipEvent_t e2 = e == hipSuccess ? prof_mark(c, s) : nullptr;
+    if (e == hipSuccess) e = homs::launch_fp4_row_consts(n, c->words, L.hv, L.rowk, s);
     prof_span(c, e0, e1, homs::kProfPrep);
     prof_span(c, e1, e2, homs::kProfEncode);
     uint32_t flags = 0;
@@ -1687,6 +1690,7 @@ homs_status homs_library_load(homs_ctx* c, const char* path)
         if (e == hipSuccess) e = homs::dev_malloc(&L.charge, (size_t)n);
         if (e == hipSuccess) e = homs::dev_malloc(&L.orig, ((size_t)n + orig_pad) * 4);
         if (e == hipSuccess) e = homs::dev_malloc(&L.slot, (size_t)n * 4);
+        if (e == hipSuccess) e = homs::dev_malloc(&L.rowk, ((size_t)n + orig_pad) * 4);
         if (e == hipSuccess) e = hipMemcpy(L.orig, orig.data(), (size_t)n * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(L.orig + n, 0, orig_pad * 4);
         if (e == hipSuccess) e = hipMemcpy(L.pmz, pmz.data(), (size_t)n * 8, hipMemcpyHostToDevice);
@@ -1701,6 +1705,13 @@ homs_status homs_library_load(homs_ctx* c, const char* path)
     if (homs_status s = read_device(c, f, L.hv, (size_t)n * c->words * 4, buf)) {
         free_library(L);
         return s;
+    }
+    if (n > 0) {
+        const hipError_t ek = homs::launch_fp4_row_consts(n, c->words, L.hv, L.rowk, nullptr);
+        if (ek != hipSuccess) {
+            free_library(L);
+            return hip_fail(c, ek, "library load");
+        }
     }
     if (!f.finish(&why)) {
         free_library(L);

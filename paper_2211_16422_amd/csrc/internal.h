@@ -23,6 +23,7 @@ struct Library {
     int8_t* charge = nullptr;    // [n] sorted charge (all 0 when charge is ignored)
     uint32_t* orig = nullptr;    // [n] library index of each sorted row
     uint32_t* slot = nullptr;    // [n] sorted row of each library index
+    float* rowk = nullptr;       // [n + pad] the fp4 search's per-row constant K
 };
 
 struct Workspace {
@@ -175,6 +176,9 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
                               const uint32_t* qperm, const int64_t* lo, const int64_t* hi,
                               const int64_t* tile_lo, const int64_t* tile_hi, int32_t* qoff,
                               uint64_t* keys, hipStream_t s);
+// the fp4 form's per-row constants K of n rows of hv, then search_mfma_row_pad() zeros
+hipError_t launch_fp4_row_consts(int64_t n, uint32_t words, const uint32_t* hv, float* rowk,
+                                 hipStream_t s);
 hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
                                     int32_t* qoff, hipStream_t s);
 

@@ -15,18 +15,20 @@
 // one with another constant); the int32 dot product is 4096 (D - 2H), at most
 // 2^27 in magnitude, and is shifted down by 12 before the same epilogue.
 //
-// fp4 (half the operand bytes and half the matrix cycles of fp8): the query
-// side is symmetric, component c of class m = c mod 4 being (-1)^b beta_m
-// with beta = (4, 2, 1, 1); the library side is not, being u_m + a delta_m
-// with (u, u + delta) = (-1, -1.5), (-0, -1), (-0, -2), (+1, -1). Every class
-// has delta_m beta_m = -2, so the dot product is sum over classes of
-// u beta (n - 2|b|) + 2|b| - 2H: a per-query constant Q minus 2H, with
-// Q = -3D/4 + 10|b|_0 + 2|b|_1 + 2|b|_2 (|b|_m: the query's set bits of class
-// m). Every product is an integer (+-1, +-2, +-4, +-6 or 0) and every sum
-// is below 2^15, so H = (Q - <x, y>) / 2 holds exactly. The point of the
-// asymmetry: a library-side bit stays where it is in its word (one v_bfi_b32
-// per 8 components, no shift), which takes 3 of every 7 expansion operations
-// off the side that is expanded twice as often.
+// fp4 (half the operand bytes and half the matrix cycles of fp8): both sides
+// map component c of class m = c mod 4 with bit x to u_m + 2 x s_m, where
+// (u, u + 2 s) = (4, 6), (2, 4), (0, 2), (1, -1): each pair differs in bit m
+// of its e2m1 code alone (mantissa, exponent low, exponent high, sign), so
+// the bit stays where it is in its word and one v_bfi_b32 (a v_and_b32 for
+// class 2) expands 8 components, with no shift on either side. A product is
+// u^2 + 2 u s (x + y) + 4 x y, so <x, y> = 21D/4 + sum_m 2 u_m s_m (|a|_m +
+// |b|_m) + 4 a.b (|a|_m: a row's set bits of class m), and with H = |a| +
+// |b| - 2 a.b: 2H = K(a) + Q(b) - <x, y>, where K(a) = 10 |a|_0 + 6 |a|_1 +
+// 2 |a|_2 is a per-row constant (stored with the library as a float) and
+// Q(b) = 21D/4 + 10 |b|_0 + 6 |b|_1 + 2 |b|_2 a per-query constant. The
+// epilogue works on t = <x, y> - K (largest t = smallest H; H = (Q - t) / 2).
+// Every product is an integer of magnitude <= 36 and every sum below 2^24,
+// so t and H are exact.
 //
 // Data movement: the packed bits of the block's 256 library rows and 256
 // query rows move into LDS in stages of 4 groups (1,024 components, one
@@ -103,33 +105,23 @@ __device__ __forceinline__ v8i expand_pm1(uint32_t w, uint32_t sel, uint32_t one
 
 // 32 packed bits -> 32 fp4 e2m1 nibbles in the low four dwords of the operand
 // (the fp4 form reads no others); nibble j of dword m is component m + 4 j of
-// the word, the same order on both sides. Query side: the bit moves to the
-// sign position (one shift and one bit insert per dword) of magnitude
-// beta_m = 4, 2, 1, 1 (mag[m] = 0x66666666, 0x44444444, 0x22222222,
-// 0x22222222). Library side: the bit stays in place (one bit insert per
-// dword) and selects between u_m and u_m + delta_m (sel[m] = 0x11111111 << m,
-// base[m] = 0xAAAAAAAA, 0x88888888, 0x88888888, 0x22222222).
+// the word, the same order and the same map on both sides: the bit stays in
+// place (bit m of the nibble) and selects between the codes of u_m and
+// u_m + 2 s_m (sel[m] = 0x11111111 << m, base[m] = 0x66666666 (4.0),
+// 0x44444444 (2.0), 0 (0.0), 0x22222222 (1.0)).
 struct Fp4Consts {
-  uint32_t c11, c22, c44, c88, cAA, c66;  // kept in VGPRs (VOP3 takes no literals)
+  uint32_t c11, c22, c44, c88, c66;  // kept in VGPRs (VOP3 takes no literals)
 };
 __device__ __forceinline__ uint32_t bfi(uint32_t sel, uint32_t x, uint32_t y) {
   uint32_t r;
   asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(x), "v"(y));
   return r;
 }
-__device__ __forceinline__ v8i expand_query_fp4(uint32_t w, const Fp4Consts& k) {
+__device__ __forceinline__ v8i expand_fp4(uint32_t w, const Fp4Consts& k) {
   v8i o = v8i{0};
-  o[0] = (int)bfi(k.c88, w << 3, k.c66);
-  o[1] = (int)bfi(k.c88, w << 2, k.c44);
-  o[2] = (int)bfi(k.c88, w << 1, k.c22);
-  o[3] = (int)bfi(k.c88, w, k.c22);
-  return o;
-}
-__device__ __forceinline__ v8i expand_lib_fp4(uint32_t w, const Fp4Consts& k) {
-  v8i o = v8i{0};
-  o[0] = (int)bfi(k.c11, w, k.cAA);
-  o[1] = (int)bfi(k.c22, w, k.c88);
-  o[2] = (int)bfi(k.c44, w, k.c88);
+  o[0] = (int)bfi(k.c11, w, k.c66);
+  o[1] = (int)bfi(k.c22, w, k.c44);
+  o[2] = (int)(w & k.c44);
   o[3] = (int)bfi(k.c88, w, k.c22);
   return o;
 }
@@ -154,15 +146,22 @@ __device__ __forceinline__ uint32_t* orig_lds() {
   __shared__ __attribute__((aligned(16))) uint32_t buf[2 * Layout8::NW * Layout8::TR * 32];
   return buf;
 }
+// the fp4 row constants K of the same rows
+__device__ __forceinline__ float* rowk_lds() {
+  __shared__ __attribute__((aligned(16))) float buf[2 * Layout8::NW * Layout8::TR * 32];
+  return buf;
+}
 
-// qoff: the per-query constant Q of the fp4 form (by query index; unused by fp8
+// qoff / rowk: the per-query constant Q and the per-row constant K of the fp4
+// form (by query index and by sorted row, rowk padded like orig; unused by fp8
 // and int8)
 template <int F, int kSG, bool kAhead, class L>
 __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
     uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
-    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
+    const int32_t* __restrict__ qoff, const float* __restrict__ rowk,
+    uint64_t* __restrict__ keys)
 {
   constexpr int MR = kRows, NQ = kQueries;
   constexpr int WR = L::WR, WQ = L::WQ, TR = L::TR, TQ = L::TQ, RPW = L::kLoadRows;
@@ -179,9 +178,11 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   const int h = l >> 5;
   char* const lds = stage_lds();
   uint32_t* const s_orig = orig_lds();
+  float* const s_rowk = rowk_lds();
 
   // query columns of this lane (B rows and epilogue columns coincide);
-  // distance = (Q - dot) / 2 with Q = D (fp8) or the query's constant (fp4)
+  // distance = (Q - t) / 2: t the dot product and Q = D (fp8, int8), or t the
+  // dot product minus the row's K and Q the query's constant (fp4)
   uint32_t qlo[TQ], qhi[TQ], qid[TQ];
   int Q[TQ];
   uint64_t bk[TQ];
@@ -224,12 +225,11 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
   const uint32_t nblk = (b - a + MR - 1) / MR;
   const uint32_t total = nblk * SPB;
   uint32_t sel = 0x80808080u, one = F == kFmtI8 ? 0x40404040u : 0x38383838u;  // int8 / fp8
-  Fp4Consts k4{0x11111111u, 0x22222222u, 0x44444444u, 0x88888888u, 0xAAAAAAAAu, 0x66666666u};
+  Fp4Consts k4{0x11111111u, 0x22222222u, 0x44444444u, 0x88888888u, 0x66666666u};
   if constexpr (F != kFmtF4)
     asm volatile("" : "+v"(sel), "+v"(one));  // keep in VGPRs
   else
-    asm volatile("" : "+v"(k4.c11), "+v"(k4.c22), "+v"(k4.c44), "+v"(k4.c88), "+v"(k4.cAA),
-                 "+v"(k4.c66));
+    asm volatile("" : "+v"(k4.c11), "+v"(k4.c22), "+v"(k4.c44), "+v"(k4.c88), "+v"(k4.c66));
 
   // piece loaded by this lane in instruction x: LDS position l % kP of row
   // w * RPW + x * kRPI + l / kP holds piece position ^ f(row)
@@ -255,6 +255,14 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
                      :
                      : "v"(voff), "s"(orig), "s"(m0)
                      : "memory", "m0");
+        if constexpr (F == kFmtF4) {  // the rows' K, same positions (rowk is padded)
+          const uint32_t mk = __builtin_amdgcn_readfirstlane(
+              (uint32_t)(uintptr_t)(s_rowk + ((B & 1) * WR * WQ + w) * TR * 32 + 64 * x));
+          asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1"
+                       :
+                       : "v"(voff), "s"(rowk), "s"(mk)
+                       : "memory", "m0");
+        }
       }
     }
     char* const sA = lds + (S & 1) * kBuf;
@@ -349,7 +357,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
         for (int j = 0; j < TQ; ++j) {
           const uint32_t x = st == 0 ? cb[j].x : st == 1 ? cb[j].y : st == 2 ? cb[j].z : cb[j].w;
           if constexpr (F == kFmtF4)
-            bv[j] = expand_query_fp4(x, k4);
+            bv[j] = expand_fp4(x, k4);
           else
             bv[j] = expand_pm1(x, sel, one);
         }
@@ -358,7 +366,7 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
           const uint32_t x = st == 0 ? ca[i].x : st == 1 ? ca[i].y : st == 2 ? ca[i].z : ca[i].w;
           v8i av;
           if constexpr (F == kFmtF4)
-            av = expand_lib_fp4(x, k4);
+            av = expand_fp4(x, k4);
           else
             av = expand_pm1(x, sel, one);
 #pragma unroll
@@ -387,6 +395,23 @@ __device__ __forceinline__ void tile_rows_staged(uint32_t words, int64_t nq,
     const uint32_t blk = S / SPB;
     const uint32_t base = a + blk * MR + wr * TR * 32;
     const uint32_t* so = s_orig + ((blk & 1) * WR * WQ + w) * TR * 32 + 4 * (l >> 5);
+    if constexpr (F == kFmtF4) {
+      // fp4: t = <x, y> - K(row) in place (the accumulators restart with the
+      // next block); from here on the epilogue is that of fp8 with t for the
+      // dot product and Q(b) for D
+      const float* sk = s_rowk + ((blk & 1) * WR * WQ + w) * TR * 32 + 4 * (l >> 5);
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) {
+          const float4 kq = *(const float4*)(sk + i * 32 + 8 * rg);
+          const float kv[4] = {kq.x, kq.y, kq.z, kq.w};
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4)
+#pragma unroll
+            for (int j = 0; j < TQ; ++j) acc[i][j][4 * rg + r4] -= kv[r4];
+        }
+    }
     bool inner = base + TR * 32 <= b;
 #pragma unroll
     for (int j = 0; j < TQ; ++j)
@@ -468,14 +493,15 @@ __device__ __forceinline__ void tile_rows(uint32_t words, int64_t nq,
     const uint32_t* __restrict__ q_hv, const uint32_t* __restrict__ qperm,
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t tile, uint32_t a,
     uint32_t b, const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
-    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys)
+    const int32_t* __restrict__ qoff, const float* __restrict__ rowk,
+    uint64_t* __restrict__ keys)
 {
   if (words % 32 == 0)
     tile_rows_staged<F, 4, kAhead, L>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig,
-                                      qoff, keys);
+                                      qoff, rowk, keys);
   else
     tile_rows_staged<F, 2, kAhead, L>(words, nq, q_hv, qperm, lo, hi, tile, a, b, lib, orig,
-                                      qoff, keys);
+                                      qoff, rowk, keys);
 }
 
 }  // namespace mfd

@@ -199,7 +199,7 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                          uint32_t chunk_rows, uint32_t narrow_group, Plan* __restrict__ plan,
                          const uint32_t* __restrict__ lib_hv,
                          const uint32_t* __restrict__ lib_orig, const int32_t* __restrict__ qoff,
-                         uint64_t* __restrict__ keys)
+                         const float* __restrict__ rowk, uint64_t* __restrict__ keys)
 {
     static_assert(popc::kTile == mfd::kQueries, "all engines use 256-query tiles");
     constexpr int kFormat = ENGINE == HOMS_ENGINE_MFMA_F4 ? 4 : 0;  // f8f6f4 element format
@@ -234,7 +234,7 @@ persistent_search_kernel(uint32_t words, const uint32_t* __restrict__ q_hv,
                 else
                     mfd::tile_rows<kFormat>(words, (int64_t)n_wide, q_hv, order, lo, hi, tile,
                                             (uint32_t)a, (uint32_t)b, lib_hv, lib_orig, qoff,
-                                            keys);
+                                            rowk, keys);
             }
         } else {
             const int64_t first = (int64_t)n_wide + (int64_t)(item - wide_items) * narrow_group;
@@ -313,17 +313,20 @@ hipError_t launch_search_batched(const homs_ctx* c, const BatchedConfig& cfg, vo
     if (cfg.engine == HOMS_ENGINE_MFMA_F8) {
         persistent_search_kernel<HOMS_ENGINE_MFMA_F8><<<cfg.grid, mfd::kThreads, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, keys);
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, nullptr,
+            keys);
     } else if (cfg.engine == HOMS_ENGINE_MFMA_F4) {
         e = launch_fp4_query_offsets(c, nq, q_hv, qoff, s);
         if (e != hipSuccess) return e;
         persistent_search_kernel<HOMS_ENGINE_MFMA_F4><<<cfg.grid, mfd::kThreads, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, qoff, keys);
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, qoff, c->lib.rowk,
+            keys);
     } else {
         persistent_search_kernel<HOMS_ENGINE_POPCOUNT><<<cfg.grid, popc::kTile, 0, s>>>(
             c->words, q_hv, order, lo, hi, nq, tile_lo, tile_hi, tile_item, max_tiles,
-            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, keys);
+            cfg.chunk_rows, cfg.narrow_group, plan, c->lib.hv, c->lib.orig, nullptr, nullptr,
+            keys);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

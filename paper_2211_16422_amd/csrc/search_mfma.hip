@@ -53,7 +53,8 @@ __global__ __launch_bounds__(DirectLayout::kThreads, 1) void mfma_direct_kernel(
     const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
     const int64_t* __restrict__ tlo, const int64_t* __restrict__ thi,
     const uint32_t* __restrict__ lib, const uint32_t* __restrict__ orig,
-    const int32_t* __restrict__ qoff, uint64_t* __restrict__ keys, int64_t chunk, int64_t n_tiles,
+    const int32_t* __restrict__ qoff, const float* __restrict__ rowk,
+    uint64_t* __restrict__ keys, int64_t chunk, int64_t n_tiles,
     int64_t chunk_patches, int64_t patches)
 {
   const int64_t wg = blockIdx.x;
@@ -68,26 +69,42 @@ __global__ __launch_bounds__(DirectLayout::kThreads, 1) void mfma_direct_kernel(
   const int64_t b64 = min(cidx * chunk + chunk, thi[tile]);
   if (a64 >= b64) return;
   mfd::tile_rows<F, true, DirectLayout>(words, nq, q_hv, qperm, lo, hi, tile, (uint32_t)a64,
-                                        (uint32_t)b64, lib, orig, qoff, keys);
+                                        (uint32_t)b64, lib, orig, qoff, rowk, keys);
 }
 
-// The fp4 form's per-query constant Q = -3D/4 + 10 |b|_0 + 2 |b|_1 + 2 |b|_2,
-// |b|_m the query's set bits at components of class m (component mod 4), one
-// wave per query.
+// 10 |x|_0 + 6 |x|_1 + 2 |x|_2 of a packed row, |x|_m its set bits at
+// components of class m (component mod 4): the fp4 form's per-row constant
+// K (and, plus 21D/4, its per-query constant Q); one wave per row
+__device__ __forceinline__ int fp4_class_weight(const uint32_t* __restrict__ row, uint32_t words)
+{
+  const int l = threadIdx.x & 63;
+  int s = 0;
+  for (uint32_t i = l; i < words; i += 64) {
+    const uint32_t w = row[i];
+    s += 10 * __builtin_popcount(w & 0x11111111u) + 6 * __builtin_popcount(w & 0x22222222u) +
+         2 * __builtin_popcount(w & 0x44444444u);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
 __global__ __launch_bounds__(256) void fp4_query_offsets_kernel(int64_t nq, uint32_t words,
     const uint32_t* __restrict__ q_hv, int32_t* __restrict__ qoff)
 {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
   if (q >= nq) return;
-  const uint32_t* row = q_hv + (size_t)q * words;
-  int s = 0;
-  for (uint32_t i = l; i < words; i += 64) {
-    const uint32_t w = row[i];
-    s += 10 * __builtin_popcount(w & 0x11111111u) + 2 * __builtin_popcount(w & 0x66666666u);
-  }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (l == 0) qoff[q] = s - (int)(3 * words * 8);
+  const int s = fp4_class_weight(q_hv + (size_t)q * words, words);
+  if ((threadIdx.x & 63) == 0) qoff[q] = s + (int)(21 * words * 8);  // 21D/4
+}
+
+// the per-row constants, n rows, then `pad` zeros
+__global__ __launch_bounds__(256) void fp4_row_consts_kernel(int64_t n, int64_t pad, uint32_t words,
+    const uint32_t* __restrict__ hv, float* __restrict__ rowk)
+{
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n + pad) return;
+  const int s = r < n ? fp4_class_weight(hv + (size_t)r * words, words) : 0;
+  if ((threadIdx.x & 63) == 0) rowk[r] = (float)s;
 }
 
 constexpr int kMfQueries = mfd::kQueries;  // 256 per workgroup
@@ -97,6 +114,15 @@ constexpr int64_t kMfChunk = 4096;
 
 int search_mfma_tile() { return kMfQueries; }
 int64_t search_mfma_row_pad() { return mfd::kRows; }
+
+hipError_t launch_fp4_row_consts(int64_t n, uint32_t words, const uint32_t* hv, float* rowk,
+                                 hipStream_t s)
+{
+  const int64_t pad = mfd::kRows;  // the epilogue reads whole groups past the last row
+  if (n + pad <= 0) return hipSuccess;
+  fp4_row_consts_kernel<<<(uint32_t)((n + pad + 3) / 4), 256, 0, s>>>(n, pad, words, hv, rowk);
+  return hipGetLastError();
+}
 
 hipError_t launch_fp4_query_offsets(const homs_ctx* c, int64_t nq, const uint32_t* q_hv,
                                     int32_t* qoff, hipStream_t s)
@@ -124,17 +150,17 @@ hipError_t launch_search_mfma(const homs_ctx* c, int fmt, int64_t nq, const uint
     if (fmt == 0) {
         mfma_direct_kernel<mfd::kFmtI8><<<(uint32_t)blocks, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig,
-            nullptr, keys, kMfChunk, n_tiles, chunk_patches, patches);
+            nullptr, nullptr, keys, kMfChunk, n_tiles, chunk_patches, patches);
     } else if (fmt == 1) {
         mfma_direct_kernel<mfd::kFmtF8><<<(uint32_t)blocks, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig,
-            nullptr, keys, kMfChunk, n_tiles, chunk_patches, patches);
+            nullptr, nullptr, keys, kMfChunk, n_tiles, chunk_patches, patches);
     } else {
         const hipError_t e = launch_fp4_query_offsets(c, nq, q_hv, qoff, s);
         if (e != hipSuccess) return e;
         mfma_direct_kernel<mfd::kFmtF4><<<(uint32_t)blocks, block, 0, s>>>(
             c->words, nq, q_hv, qperm, lo, hi, tile_lo, tile_hi, c->lib.hv, c->lib.orig,
-            qoff, keys, kMfChunk, n_tiles, chunk_patches, patches);
+            qoff, c->lib.rowk, keys, kMfChunk, n_tiles, chunk_patches, patches);
     }
     return hipGetLastError();
 }
