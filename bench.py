@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernels_large.md). Keyed by engine and the hash of the
 # kernel's sources: valid only while the source is the one measured.
 MEASURED_TRAFFIC = {("popcount", "8a0818167cd6a169"): 4.868e12,
-                    ("mfma_fp4", "210401662af5007c"): 2.6084e+11}
+                    ("mfma_fp4", "6cc7539ab6528dd9"): 2.5363e+11}
 
 ENGINE_SOURCES = {"popcount": ("search_popc.hip", "popcount_tile.h"),
                   "mfma_fp8": ("search_mfma.hip", "mfma_direct.h"),
