@@ -166,8 +166,10 @@ homs_status homs_preprocess(const homs_params *p, int64_t n, const int64_t *h_of
  * that encoding can start from raw peaks already in device memory.
  * In:  n spectra; d_offsets[n + 1] (int64 CSR, non-decreasing, d_offsets[0]
  *      = 0); d_mz and d_intensity[d_offsets[n]] (float64, finite; intensity
- *      >= 0). A spectrum may hold at most 2048 raw peaks: a larger one gets
- *      no entries and raises device error bit 1 (homs_device_errors).
+ *      >= 0). Spectra of any size; one that would keep more than 2048 peaks
+ *      (min(peaks at or above the noise floor, top_n) > 2048, so only with
+ *      top_n above 2048) gets no entries and raises device error bit 1
+ *      (homs_device_errors).
  * Out: d_out_offsets[n + 1]; d_out_bin (int32) and d_out_level (uint8) with
  *      room for min(d_offsets[n], n * top_n) entries: per spectrum its unique
  *      bins in ascending order. All device pointers.

@@ -14,7 +14,7 @@ namespace homs {
 
 // Device-side error flag bits.
 constexpr uint32_t kErrRange = 1u;  // bin >= f or level >= Q in an encode
-constexpr uint32_t kErrPeaks = 2u;  // a spectrum too large for device preprocessing
+constexpr uint32_t kErrPeaks = 2u;  // a spectrum keeping more peaks than device preprocessing holds
 
 struct Library {
     int64_t n = 0;

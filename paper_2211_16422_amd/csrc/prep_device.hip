@@ -11,9 +11,13 @@
 // (m/z asc, position asc) order by a second rank, and colliding bins are
 // summed by the lane holding their first peak, sequentially in m/z order (the
 // order that fixes the sums' rounding); normalisation and quantisation are
-// per bin. Larger spectra, up to kPrepCap raw peaks, go to a workgroup
-// kernel with bitonic sorts in LDS and one thread for the in-order sums; a
-// spectrum beyond that raises kErrPeaks and yields no entries. Every double
+// per bin. Larger spectra go to a workgroup kernel with bitonic sorts in LDS
+// and one thread for the in-order sums; one with more than kPrepCap raw peaks
+// first has the peaks that can reach the top-N gathered into LDS (all kept
+// peaks, or, when more than kPrepCap are kept, the top_n found by a radix
+// select over (intensity desc, m/z asc, position asc) keys read from global
+// memory), and only a spectrum that would keep more than kPrepCap peaks
+// (top_n above kPrepCap) raises kErrPeaks and yields no entries. Every double
 // operation is an IEEE operation (no contraction; the device double square
 // root is correctly rounded), so results equal the host path's.
 //
@@ -76,6 +80,121 @@ __device__ void bitonic(double* a_mz, double* a_in, uint32_t* a_pos, int P, Befo
     }
 }
 
+// order-preserving key of a finite double (-0 and +0 share one)
+__device__ __forceinline__ uint64_t order_key(double x)
+{
+    if (x == 0.0) x = 0.0;
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// A spectrum of np > kPrepCap raw peaks: gathers into s_mz / s_in / s_pos
+// (count in *s_m, which starts at 0) the kept peaks (in range, not below
+// floor_i) that can reach the top-N: all of them when at most kPrepCap are
+// kept, else the T = min(kept, top_n) first under (intensity desc, m/z asc,
+// position asc), found by a radix select, 8 bits per round, over the 160-bit
+// keys (~key(intensity), key(m/z), position) read from global memory. Returns
+// false (uniform) when T exceeds kPrepCap. The whole workgroup calls it.
+__device__ bool gather_large(int64_t p0, int64_t np, const double* __restrict__ mz,
+                             const double* __restrict__ inten, const PrepArgs& pa, double floor_i,
+                             double* s_mz, double* s_in, uint32_t* s_pos, int* s_m)
+{
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_kept, s_dig, s_below, s_eq;
+    auto kept_at = [&](int64_t p, double& m, double& v) {
+        m = mz[p0 + p];
+        v = inten[p0 + p];
+        return m >= pa.mz_min && m < pa.mz_max && !(v < floor_i);
+    };
+    if (threadIdx.x == 0) s_kept = 0;
+    __syncthreads();
+    uint32_t c = 0;
+    for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
+        double m, v;
+        c += kept_at(p, m, v) ? 1u : 0u;
+    }
+    atomicAdd(&s_kept, c);
+    __syncthreads();
+    const uint32_t kept = s_kept;
+    auto put = [&](int64_t p, double m, double v) {
+        const int slot = atomicAdd(s_m, 1);
+        if (slot < kPrepCap) {  // always, by the counts above; kept as a bound
+            s_mz[slot] = m;
+            s_in[slot] = v;
+            s_pos[slot] = (uint32_t)p;
+        }
+    };
+    if (kept <= (uint32_t)kPrepCap) {  // uniform
+        for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
+            double m, v;
+            if (kept_at(p, m, v)) put(p, m, v);
+        }
+        return true;
+    }
+    uint32_t r = kept < pa.top_n ? kept : pa.top_n;  // rank sought, 1-based
+    if (r > (uint32_t)kPrepCap) return false;
+    // prefix and mask of the decided digits of the three keys
+    uint64_t pre1 = 0, msk1 = 0, pre2 = 0, msk2 = 0;
+    uint32_t pre3 = 0, msk3 = 0;
+    auto keys = [&](int64_t p, double m, double v, uint64_t& k1, uint64_t& k2, uint32_t& k3) {
+        k1 = ~order_key(v);  // descending intensity
+        k2 = order_key(m);
+        k3 = (uint32_t)p;
+    };
+    for (int d = 0; d < 20; ++d) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) s_hist[i] = 0;
+        __syncthreads();
+        for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
+            double m, v;
+            if (!kept_at(p, m, v)) continue;
+            uint64_t k1, k2;
+            uint32_t k3;
+            keys(p, m, v, k1, k2, k3);
+            if ((k1 & msk1) != pre1 || (k2 & msk2) != pre2 || (k3 & msk3) != pre3) continue;
+            const uint32_t dig = d < 8 ? (uint32_t)(k1 >> (56 - 8 * d)) & 255u
+                                 : d < 16 ? (uint32_t)(k2 >> (56 - 8 * (d - 8))) & 255u
+                                          : (k3 >> (24 - 8 * (d - 16))) & 255u;
+            atomicAdd(&s_hist[dig], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {  // the digit holding the r-th smallest key
+            uint32_t cum = 0, dg = 0;
+            while (dg < 255 && cum + s_hist[dg] < r) cum += s_hist[dg++];
+            s_dig = dg;
+            s_below = cum;
+            s_eq = s_hist[dg];
+        }
+        __syncthreads();
+        const uint32_t dig = s_dig, eq = s_eq;
+        r -= s_below;
+        if (d < 8) {
+            pre1 |= (uint64_t)dig << (56 - 8 * d);
+            msk1 |= (uint64_t)255 << (56 - 8 * d);
+        } else if (d < 16) {
+            pre2 |= (uint64_t)dig << (56 - 8 * (d - 8));
+            msk2 |= (uint64_t)255 << (56 - 8 * (d - 8));
+        } else {
+            pre3 |= dig << (24 - 8 * (d - 16));
+            msk3 |= 255u << (24 - 8 * (d - 16));
+        }
+        if (eq == r) break;  // uniform: every key sharing the prefix is taken
+    }
+    // every kept peak whose decided digits are at most the prefix: T of them
+    for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
+        double m, v;
+        if (!kept_at(p, m, v)) continue;
+        uint64_t k1, k2;
+        uint32_t k3;
+        keys(p, m, v, k1, k2, k3);
+        k1 &= msk1;
+        k2 &= msk2;
+        k3 &= msk3;
+        const bool le = k1 != pre1 ? k1 < pre1 : k2 != pre2 ? k2 < pre2 : k3 <= pre3;
+        if (le) put(p, m, v);
+    }
+    return true;
+}
+
 __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
     int write, int64_t n, const int64_t* __restrict__ off, const double* __restrict__ mz,
     const double* __restrict__ inten, PrepArgs pa, int64_t* __restrict__ counts,
@@ -90,25 +209,22 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
         const int64_t p0 = off[s];
         const int64_t np = off[s + 1] - p0;
         if (np <= kWaveCap) continue;  // the wave kernel's
-        if (np > kPrepCap) {  // uniform
-            if (threadIdx.x == 0) {
-                atomicOr(err, kErrPeaks);
-                if (write != 1) counts[s] = 0;
-            }
-            continue;
-        }
+        const bool large = np > kPrepCap;  // uniform
         if (threadIdx.x == 0) s_m = 0;
         __syncthreads();
-        // 1. m/z range; 2. the maximum intensity of the peaks in range
+        // 1. m/z range; 2. the maximum intensity of the peaks in range (those
+        // peaks go to LDS unless the spectrum is larger than LDS holds)
         double imax = 0.0;
         for (int64_t p = threadIdx.x; p < np; p += blockDim.x) {
             const double m = mz[p0 + p];
             if (m >= pa.mz_min && m < pa.mz_max) {
                 const double v = inten[p0 + p];
-                const int slot = atomicAdd(&s_m, 1);
-                s_mz[slot] = m;
-                s_in[slot] = v;
-                s_pos[slot] = (uint32_t)p;
+                if (!large) {
+                    const int slot = atomicAdd(&s_m, 1);
+                    s_mz[slot] = m;
+                    s_in[slot] = v;
+                    s_pos[slot] = (uint32_t)p;
+                }
                 imax = v > imax ? v : imax;
             }
         }
@@ -119,8 +235,19 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(
                 s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + o]);
             __syncthreads();
         }
-        const int m = s_m;
         const double floor_i = pa.noise_frac * s_red[0];
+        if (large) {
+            if (!gather_large(p0, np, mz, inten, pa, floor_i, s_mz, s_in, s_pos, &s_m)) {
+                if (threadIdx.x == 0) {
+                    atomicOr(err, kErrPeaks);
+                    if (write != 1) counts[s] = 0;
+                }
+                __syncthreads();
+                continue;
+            }
+            __syncthreads();
+        }
+        const int m = s_m < kPrepCap ? s_m : kPrepCap;
         // peaks below the noise floor sort after the kept ones (kept >= 0),
         // padding after everything
         int P = 1;

@@ -488,8 +488,9 @@ class Context:
         intensities) -> device CSR (offsets int64, bins int32, levels uint8).
 
         With `check` (the default) the context's device error flags are read (and
-        cleared) after the call, and a spectrum over the device limit of 2,048 raw
-        peaks (flag bit 1; it gets no entries) raises HomsError(HOMS_E_INVALID)."""
+        cleared) after the call, and a spectrum that would keep more than 2,048 peaks
+        (possible only with top_n above 2,048; flag bit 1; it gets no entries) raises
+        HomsError(HOMS_E_INVALID)."""
         import torch
         n = offsets.shape[0] - 1
         raw = int(offsets[-1].item()) if n > 0 else 0
@@ -509,7 +510,7 @@ class Context:
             flags = self.device_errors()
             if flags & 2:
                 raise HomsError(HOMS_E_INVALID,
-                                "homs_preprocess_device: a spectrum has more than 2048 raw peaks "
+                                "homs_preprocess_device: a spectrum keeps more than 2048 peaks "
                                 f"(device error flags {flags:#x}); it was given no entries")
             if flags:
                 raise HomsError(HOMS_E_INVALID, f"device error flags {flags:#x}")

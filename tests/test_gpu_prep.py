@@ -1,8 +1,8 @@
 """Device preprocessing (Section 3.2, Table 1) through the C ABI against the
 oracle's: every spectrum's unique bins and levels must be identical, on the
 synthetic workload and on hand-built edge cases (range boundaries, the noise
-floor, intensity and m/z ties in the top-N, colliding bins, empty and
-oversized spectra); encoding from the device output equals the oracle's
+floor, intensity and m/z ties in the top-N, colliding bins, empty spectra,
+spectra larger than LDS holds, and the one case that is refused); encoding from the device output equals the oracle's
 encoding of the raw spectra."""
 import numpy as np
 import pytest
@@ -85,24 +85,65 @@ def test_edge_cases_match_oracle(ctx):
     assert ctx.device_errors() == 0
 
 
-def test_oversized_spectrum_is_flagged(ctx):
+def test_large_spectra_match_oracle(ctx):
+    """Spectra with more raw peaks than the workgroup kernel holds in LDS
+    (2,048): the top-N candidates are gathered by a radix select over
+    (intensity desc, m/z asc, position asc) keys. Cases: kept peaks under the
+    LDS size (most below the noise floor), many kept peaks with distinct
+    intensities, ties of intensity across the top_n boundary (broken by m/z,
+    then by position, including equal m/z), and one spectrum of 40,000 peaks;
+    every one must equal the oracle."""
     rng = np.random.default_rng(3)
+    n = 5000
+    floor_heavy = (list(rng.uniform(101, 1500, n)),
+                   [100.0] * 100 + list(rng.uniform(0.0, 0.5, n - 100)))   # 100 kept of 5000
+    distinct = (list(rng.uniform(101, 1500, n)), list(rng.lognormal(0, 1, n)))
+    tie_i = (list(rng.uniform(101, 1500, n)), [7.0] * 30 + [3.0] * 40 + [1.0] * (n - 70))
+    mz_dup = [float(x) for x in np.round(rng.uniform(101, 1500, n), 1)]   # many equal m/z
+    tie_mz = (mz_dup, [7.0] * 20 + [5.0] * 60 + [1.0] * (n - 80))
+    same = ([800.0] * 3000, [2.0] * 3000)                                 # one m/z, one intensity
+    out_of_range = (list(rng.uniform(1500, 2000, 2500)) + [300.0, 301.0], [1.0] * 2502)
+    huge = (list(rng.uniform(101, 1500, 40000)), list(rng.lognormal(0, 1, 40000)))
     small = (list(rng.uniform(101, 1500, 30)), list(rng.lognormal(0, 1, 30)))
-    big = (list(rng.uniform(101, 1500, 2049)), list(rng.lognormal(0, 1, 2049)))
-    off, mz, inten = _pack([small, big, small])
+    spectra = [small, floor_heavy, distinct, tie_i, tie_mz, small, same, out_of_range, huge]
+    off, mz, inten = _pack(spectra)
+    want = oracle.preprocess(off, mz, inten, oracle.Params(dim=2048))
+    _same(_device(ctx, off, mz, inten), want)
+    assert ctx.device_errors() == 0
+
+
+def test_too_many_kept_peaks_are_flagged():
+    """With top_n above the LDS size (3,000), a spectrum keeping more than
+    2,048 peaks cannot be processed: it gets no entries, device error bit 1
+    is set and the binding raises; the spectra around it are unaffected, and
+    a large spectrum keeping fewer peaks still matches the oracle."""
     h = _h()
-    with pytest.raises(h.HomsError) as e:  # the binding reads the flag and raises
-        _device(ctx, off, mz, inten)
-    assert e.value.status == h.HOMS_E_INVALID and "2048" in str(e.value)
-    o, b, l = _device(ctx, off, mz, inten, check=False)
-    assert ctx.device_errors() & 2
-    assert o[2] - o[1] == 0  # the oversized spectrum gets no entries
-    want = oracle.preprocess(*_pack([small]), oracle.Params(dim=2048))
-    assert np.array_equal(b[o[0]:o[1]], want[1]) and np.array_equal(b[o[2]:o[3]], want[1])
-    assert np.array_equal(l[o[0]:o[1]], want[2])
-    # no spectra at all
-    o, b, l = _device(ctx, [0], [], [])
-    assert list(o) == [0] and b.size == 0
+    c = h.Context(h.Params(dim=2048, top_n=3000))
+    try:
+        rng = np.random.default_rng(4)
+        small = (list(rng.uniform(101, 1500, 30)), list(rng.lognormal(0, 1, 30)))
+        big = (list(rng.uniform(101, 1500, 2600)), list(rng.uniform(1.0, 2.0, 2600)))
+        few = (list(rng.uniform(101, 1500, 2600)),
+               [50.0] * 1000 + list(rng.uniform(0.0, 0.4, 1600)))          # 1,000 kept
+        off, mz, inten = _pack([small, big, small])
+        with pytest.raises(h.HomsError) as e:  # the binding reads the flag and raises
+            _device(c, off, mz, inten)
+        assert e.value.status == h.HOMS_E_INVALID and "2048" in str(e.value)
+        o, b, l = _device(c, off, mz, inten, check=False)
+        assert c.device_errors() & 2
+        assert o[2] - o[1] == 0  # the oversized spectrum gets no entries
+        want = oracle.preprocess(*_pack([small]), oracle.Params(dim=2048, top_n=3000))
+        assert np.array_equal(b[o[0]:o[1]], want[1]) and np.array_equal(b[o[2]:o[3]], want[1])
+        assert np.array_equal(l[o[0]:o[1]], want[2])
+        off, mz, inten = _pack([small, few])
+        want = oracle.preprocess(off, mz, inten, oracle.Params(dim=2048, top_n=3000))
+        _same(_device(c, off, mz, inten), want)
+        assert c.device_errors() == 0
+        # no spectra at all
+        o, b, l = _device(c, [0], [], [])
+        assert list(o) == [0] and b.size == 0
+    finally:
+        c.close()
 
 
 def test_encode_from_raw_on_device(ctx):
