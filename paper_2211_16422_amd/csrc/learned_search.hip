@@ -820,8 +820,8 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
 }
 
 // One workgroup per query of the pass: the k largest keys of its buffer, in
-// descending order. When more than kMaxK candidates were kept, the keys stay
-// in registers; a radix select over the scores (8 bits per round, each
+// descending order. When more than twice k candidates were kept, the keys
+// stay in registers; a radix select over the scores (8 bits per round, each
 // round's digit found by one wave) gives the k-th largest score and how many
 // keys share it, a second select over library indices runs only among those
 // ties when not all of them are kept, and only the k kept keys are translated
@@ -858,8 +858,12 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
     auto lib_key = [&](uint64_t v) {
         return (v & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - lib_orig[(uint32_t)v]);
     };
+    // a buffer of at most twice the kept count (and at most kMaxK keys) is
+    // sorted whole; a larger one first has its kk-th key selected, so that
+    // only the kept keys are translated and sorted
+    const bool whole = n <= 2 * kk && n <= kMaxK;
     if (!bad && kk > 0) {  // uniform
-        if (n <= kMaxK) {
+        if (whole) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) s_sel[i] = lib_key(keys[i]);
         } else {
             constexpr int kPer = kCapacity / kThreads;
@@ -933,7 +937,7 @@ __global__ __launch_bounds__(kThreads) void select_kernel(
             }
         }
         __syncthreads();
-        const int m = n <= kMaxK ? n : kk;  // keys now in s_sel
+        const int m = whole ? n : kk;  // keys now in s_sel
         int np = 1;
         while (np < m) np <<= 1;
         for (int i = m + threadIdx.x; i < np; i += blockDim.x) s_sel[i] = 0ull;
