@@ -55,6 +55,7 @@ constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kCountStride = 32;
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 8192;  // library rows per collection workgroup
+constexpr int kRowGroups = 2;  // row groups of a collection workgroup (64-row block steps)
 constexpr int kThreads = 256;
 constexpr int64_t kFallbackRows = 512;   // window rows per wave in the exhaustive fallback
 
@@ -401,22 +402,27 @@ __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
     if (threadIdx.x == 0) thr2[p] = fmaxf(t1, fkey_inv(prefix));
 }
 
-// Scores 128 library rows x 128 m/z-ordered queries per block step on matrix
-// cores and appends every in-window pair at or above the query's threshold.
+// Scores BR = 32 NWR library rows x 128 m/z-ordered queries per block step on
+// matrix cores and appends every in-window pair at or above the query's
+// threshold.
 //
 // Operands are the scoring embeddings as E4M3 codes of 16 e (one byte per
 // component, v_mfma_f32_32x32x64_f8f6f4, fp32 accumulation): every product
 // of two codes is exact in fp32, and the accumulator holds 256 times the
 // score of the rounded embeddings.
 //
-// Eight waves, two per SIMD: wave (wr, wn) owns rows 32 wr .. + 31 of each
+// 2 NWR waves, two per SIMD: wave (wr, wn) owns rows 32 wr .. + 31 of each
 // block and the 64 queries of half wn (two 32-query tiles), whose codes are
 // its B operands for the whole chunk (E / 64 steps of 32 bytes per tile), so
 // every A operand read from LDS feeds two matrix instructions. Library rows
 // stream through four LDS buffers filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4, no staging registers): one load moves 1 KB (64
-// lanes x 16 bytes) of a block's rows, so a 128-row block of E-byte rows
-// takes E / 64 loads per wave. Per block step, the block's A operands are in
+// lanes x 16 bytes) of a block's rows, so a block of BR E-byte rows takes
+// E / 64 loads per wave. With NWR = 2 (64-row steps, four waves) two
+// workgroups share a compute unit, each with its own barrier, so one
+// workgroup's waves keep the matrix cores busy while the other's wait at
+// theirs; NWR = 4 (128-row steps, eight waves) is one workgroup per compute
+// unit. Per block step, the block's A operands are in
 // registers (read from LDS one step ahead), the next block waits in LDS and
 // two more are in flight; one barrier per block both publishes the landed
 // block and frees the buffer of the block in registers. The 16-byte piece
@@ -457,8 +463,8 @@ __device__ __forceinline__ float max16(const gemm::f32x16& v)
     return fmaxf(fmaxf(fmaxf(a, b), c), fmaxf(fmaxf(d, e), v[15]));
 }
 
-template <int E, int pass>
-__global__ __launch_bounds__(512, 1) void collect_kernel(
+template <int E, int pass, int NWR>
+__global__ __launch_bounds__(64 * 2 * NWR, 2) void collect_kernel(
     int64_t q_begin, int64_t q_end, const uint8_t* __restrict__ q_sorted8,
     const uint32_t* __restrict__ qperm, const int64_t* __restrict__ lo,
     const int64_t* __restrict__ hi, const float* __restrict__ thr,
@@ -471,12 +477,15 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     constexpr int PPK = 16 / KS;                  // epilogue positions per step
     constexpr int P = E / 16;                     // 16-byte pieces per row
     constexpr int RPS = 16 / P;                   // rows sharing one swizzle value
-    constexpr int NW = 8;                         // waves
+    constexpr int NW = 2 * NWR;                   // waves: NWR row groups x 2 query halves
+    constexpr int BR = 32 * NWR;                  // rows per block step
+    constexpr uint32_t S = 128 / BR;              // block steps per 128-row pass block
     constexpr int NL = E / 64;                    // direct loads per wave per block
     constexpr float kScoreScale2 = kScoreScale * kScoreScale;
     constexpr int kBufs = 4;                      // LDS block buffers: kBufs blocks in flight
     static_assert(KS * PPK == 16 && NL >= 1, "E in {64, 128, 256}");
-    __shared__ __attribute__((aligned(16))) uint8_t sA[kBufs][128 * E];
+    static_assert(NWR == 2 || NWR == 4, "64- or 128-row block steps");
+    __shared__ __attribute__((aligned(16))) uint8_t sA[kBufs][BR * E];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
     // Chunks are fixed row ranges of the sorted library, clipped to the
@@ -499,46 +508,51 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
     // the wave index in a scalar register: everything derived from it is
     // wave-uniform scalar work
     const int t = threadIdx.x, l = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wr = w & 3, wn = w >> 2;
+    const int wr = w % NWR, wn = w / NWR;
     const int64_t p0 = q_begin + tile * kTileQ;  // first sorted query of the tile
-    // This pass's absolute 128-row blocks meeting [c0, c1): pass 0 the
-    // multiples of kPassStride, pass 1 the others. Rows of a block below c0
-    // lie below every window of the tile (c0 is the chunk's first row or the
-    // tile's lowest window start) and are masked like any row outside a window.
-    const int64_t g_lo = c0 / 128, g_hi = (c1 + 127) / 128;
-    const int64_t f0 = (g_lo + kPassStride - 1) / kPassStride * kPassStride;
-    const int64_t n0 = f0 < g_hi ? (g_hi - 1 - f0) / kPassStride + 1 : 0;
+    // This pass's BR-row blocks meeting [c0, c1), in the absolute 128-row
+    // blocks of the pass (pass 0 the multiples of kPassStride, pass 1 the
+    // others): block g lies in pass-0 block g / S when g mod G < S. Rows of a
+    // block below c0 lie below every window of the tile (c0 is the chunk's
+    // first row or the tile's lowest window start) and are masked like any
+    // row outside a window.
+    constexpr int64_t G = kPassStride * S;
+    const int64_t g_lo = c0 / BR, g_hi = (c1 + BR - 1) / BR;
+    auto below0 = [](int64_t x) { return x / G * S + min(x % G, (int64_t)S); };
+    const int64_t n0 = below0(g_hi) - below0(g_lo);
     const int nblk = (int)(pass == 0 ? n0 : (g_hi - g_lo) - n0);
     if (nblk == 0) return;
     // The pass's blocks in order (32-bit: the library has fewer than 2^31
     // rows): two walkers, one for the loads (kBufs - 1 blocks ahead) and one
     // for the epilogue, each stepping to the next block of the pass.
-    const uint32_t first = pass == 0 ? (uint32_t)f0
-                                     : (uint32_t)(g_lo % kPassStride == 0 ? g_lo + 1 : g_lo);
+    const bool lo_in0 = g_lo % G < (int64_t)S;
+    const uint32_t first =
+        pass == 0 ? (uint32_t)(lo_in0 ? g_lo : (g_lo / G + 1) * G)
+                  : (uint32_t)(lo_in0 ? g_lo - g_lo % G + S : g_lo);
     auto next_block = [&](uint32_t g) -> uint32_t {
-        if (pass == 0) return g + (uint32_t)kPassStride;
         g += 1;
-        return g % kPassStride == 0 ? g + 1 : g;
+        if (pass == 0) return g % (uint32_t)G == S ? g + (uint32_t)(G - S) : g;
+        return g % (uint32_t)G == 0 ? g + S : g;
     };
     uint32_t g_issue = first, g_epi = first;
     // the pass's last block in the chunk: the loads issued for block steps
     // past the end re-read it into a buffer that is never scored, so that
     // every step waits for the same number of loads, with no branch
-    const uint32_t g_last =
-        pass == 0 ? (uint32_t)(f0 + (n0 - 1) * kPassStride)
-                  : (uint32_t)((g_hi - 1) % kPassStride == 0 ? g_hi - 2 : g_hi - 1);
+    const int64_t y = g_hi - 1, ym = y % G;
+    const uint32_t g_last = pass == 0 ? (uint32_t)(ym < (int64_t)S ? y : y - ym + S - 1)
+                                      : (uint32_t)(ym >= (int64_t)S ? y : y - ym - 1);
 
-    // rows [128 g, + 128) of the block g_issue points to into sA[b % kBufs]:
+    // rows [BR g, + BR) of the block g_issue points to into sA[b % kBufs]:
     // load x of wave w fills bytes [1024 (NL w + x), + 1024) of the buffer
     // (the destination of a direct load is M0 + 16 x lane), lane l the slot
     // of row R = o / E, o the byte offset of the lane, with the row's piece
     // (slot ^ swz(R)); rows past c1 repeat the last row
     auto issue = [&](int b) {  // block b, the one g_issue points to
-        const uint32_t mb = (b < nblk ? g_issue : g_last) * 128u;
+        const uint32_t mb = (b < nblk ? g_issue : g_last) * (uint32_t)BR;
         g_issue = next_block(g_issue);
         const uint32_t base = (uint32_t)(uintptr_t)&sA[b % kBufs][0];
         const uint8_t* gbase = lib_emb8 + (size_t)mb * E;  // wave-uniform
-        const int last = (int)min(127u, e1 - 1u - mb);
+        const int last = (int)min((uint32_t)BR - 1u, e1 - 1u - mb);
 #pragma unroll
         for (int x = 0; x < NL; ++x) {
             const int ci = w * NL + x;
@@ -724,7 +738,7 @@ __global__ __launch_bounds__(512, 1) void collect_kernel(
         }
     };
     auto block_info = [&](uint32_t& gl, bool& fast) {  // the block g_epi points to
-        const uint32_t wb = g_epi * 128 + wr * 32;
+        const uint32_t wb = g_epi * (uint32_t)BR + wr * 32;
         g_epi = next_block(g_epi);
         gl = wb + 4u * (uint32_t)(l >> 5);
         fast = wb >= wlo && wb + 32 <= whi;
@@ -1147,18 +1161,14 @@ hipError_t launch_search_learned(const homs_ctx* c, const homs_model* m, void* s
         const uint32_t cgrid = (uint32_t)cwg;
         auto collect = [&](auto pass_tag, const float* t) {
             constexpr int P = decltype(pass_tag)::value;
-            if (E == 256)
-                collect_kernel<256, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                             tlo, thi, m->lib_emb8, count, buf,
-                                                             tiles, max_chunks);
-            else if (E == 128)
-                collect_kernel<128, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                             tlo, thi, m->lib_emb8, count, buf,
-                                                             tiles, max_chunks);
-            else
-                collect_kernel<64, P><<<cgrid, 512, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t,
-                                                            tlo, thi, m->lib_emb8, count, buf,
-                                                            tiles, max_chunks);
+            constexpr int nt = 128 * kRowGroups;
+            auto go = [&](auto kern) {
+                kern<<<cgrid, nt, 0, s>>>(b0, b1, q_sorted8, qperm, lo, hi, t, tlo, thi,
+                                          m->lib_emb8, count, buf, tiles, max_chunks);
+            };
+            if (E == 256) go(collect_kernel<256, P, kRowGroups>);
+            else if (E == 128) go(collect_kernel<128, P, kRowGroups>);
+            else go(collect_kernel<64, P, kRowGroups>);
         };
         // pass 0 with the sampled threshold, the refined threshold from its
         // hits, pass 1 with the refined one (same buffers, appended)
