@@ -55,7 +55,7 @@ constexpr int kCapacity = 8192;  // buffer entries per query
 constexpr int kCountStride = 32;
 constexpr int kTileQ = 128;      // queries per collection workgroup
 constexpr int64_t kCollectChunk = 8192;  // library rows per collection workgroup
-constexpr int kRowGroups = 2;  // row groups of a collection workgroup (64-row block steps)
+constexpr int kRowGroups = 1;  // row groups of a collection workgroup (32-row block steps)
 constexpr int kThreads = 256;
 constexpr int64_t kFallbackRows = 512;   // window rows per wave in the exhaustive fallback
 
@@ -411,19 +411,22 @@ __global__ __launch_bounds__(kThreads) void refine_threshold_kernel(
 // of two codes is exact in fp32, and the accumulator holds 256 times the
 // score of the rounded embeddings.
 //
-// 2 NWR waves, two per SIMD: wave (wr, wn) owns rows 32 wr .. + 31 of each
-// block and the 64 queries of half wn (two 32-query tiles), whose codes are
-// its B operands for the whole chunk (E / 64 steps of 32 bytes per tile), so
-// every A operand read from LDS feeds two matrix instructions. Library rows
+// 2 NWR waves per workgroup, two per SIMD: wave (wr, wn) owns rows 32 wr ..
+// + 31 of each block and the 64 queries of half wn (two 32-query tiles),
+// whose codes are its B operands for the whole chunk (E / 64 steps of 32
+// bytes per tile), so every A operand read from LDS feeds two matrix
+// instructions. Library rows
 // stream through four LDS buffers filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4, no staging registers): one load moves 1 KB (64
 // lanes x 16 bytes) of a block's rows, so a block of BR E-byte rows takes
-// E / 64 loads per wave. With NWR = 2 (64-row steps, four waves) two
-// workgroups share a compute unit, each with its own barrier, so one
-// workgroup's waves keep the matrix cores busy while the other's wait at
-// theirs; NWR = 4 (128-row steps, eight waves) is one workgroup per compute
-// unit. Per block step, the block's A operands are in
-// registers (read from LDS one step ahead), the next block waits in LDS and
+// E / 64 loads per wave. The barrier of a block step couples only the waves
+// of one workgroup: with NWR = 1 (32-row steps, two waves) four workgroups
+// share a compute unit and the matrix cores run the waves of the others
+// while one workgroup waits at its barrier (with 1M + 1M rows and 100k
+// queries the scoring takes 22.4 ms with NWR = 2 and 21.0 ms with NWR = 1,
+// against 27.3 ms with NWR = 4, one workgroup per compute unit). Per block
+// step, the block's A operands are in registers (read from LDS one step
+// ahead), the next block waits in LDS and
 // two more are in flight; one barrier per block both publishes the landed
 // block and frees the buffer of the block in registers. The 16-byte piece
 // p of row R sits at slot p ^ swz(R) of the row, swz(R) = (R / (16 / P)) mod
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(64 * 2 * NWR, 2) void collect_kernel(
     constexpr float kScoreScale2 = kScoreScale * kScoreScale;
     constexpr int kBufs = 4;                      // LDS block buffers: kBufs blocks in flight
     static_assert(KS * PPK == 16 && NL >= 1, "E in {64, 128, 256}");
-    static_assert(NWR == 2 || NWR == 4, "64- or 128-row block steps");
+    static_assert(NWR == 1 || NWR == 2 || NWR == 4, "32-, 64- or 128-row block steps");
     __shared__ __attribute__((aligned(16))) uint8_t sA[kBufs][BR * E];
     __shared__ uint64_t s_key[NW][kWaveList];
     __shared__ uint8_t s_col[NW][kWaveList];  // query of the entry within the tile
