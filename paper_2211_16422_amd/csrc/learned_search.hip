@@ -10,30 +10,32 @@
 //  1. threshold: per tile of 128 m/z-ordered queries, score a regular sample
 //     of the union of its windows (every 2^j-th sorted row, at most kSample
 //     rows) on matrix cores; per query take the r-th largest of its in-window
-//     sample scores (radix select), r chosen so that about kCapacity / 4
-//     window candidates are expected at or above it (a quarter of the
-//     buffer: with r of at least 8 on the largest windows, both overflow and
-//     keeping fewer than k are far in the tails); windows of at most kSample
-//     (= kCapacity) candidates keep everything;
+//     sample scores (radix select), r chosen so that about t1 window
+//     candidates are expected at or above it (t1 between a quarter and a half
+//     of the kCapacity buffer, growing with k; see shortlist_targets);
+//     windows of at most kSample (= kCapacity) candidates keep everything;
 //  2. collect: score every (query, candidate) pair on matrix cores (E4M3
-//     scoring embeddings, fp32 accumulation, 128 library rows x 128
-//     m/z-ordered queries per workgroup) and append in-window pairs at or
-//     above the query's threshold to its buffer of kCapacity 64-bit keys
-//     (order-preserving score << 32 | sorted row), in two passes: pass 0
-//     over every eighth absolute 128-row block with the sampled threshold;
-//     then per query a threshold refined from pass 0's hits (the r-th best
-//     of them, about 4 max(k, 64) window candidates expected above it); pass
-//     1 over the other blocks with the refined threshold, where hits are
-//     rare enough that most tiles need only one ballot;
-//  3. select: sort each buffer in LDS (bitonic, descending) and keep the k
-//     largest keys; a query whose buffer overflowed, whose sampled threshold
-//     kept fewer than min(k, window) candidates, or whose k-th kept key
-//     scores below the refined threshold (so that a better candidate of pass
-//     1 could have been missed) is flagged for the exhaustive fallback and
-//     gets no shortlist;
-//  4. rescore: one lane per shortlist entry computes the exact Hamming
-//     distance; the wave minimum of (distance << 32 | library index) is merged
-//     into the query's key;
+//     scoring embeddings, fp32 accumulation; a workgroup takes 128
+//     m/z-ordered queries and an 8,192-row chunk of the library in 32-row
+//     block steps) and append in-window pairs at or above the query's
+//     threshold to its buffer of kCapacity 64-bit keys (order-preserving
+//     score << 32 | sorted row), in two passes: pass 0 over every eighth
+//     absolute 128-row block with the sampled threshold; then per query a
+//     threshold refined from pass 0's hits (the r-th best of them, about t2
+//     window candidates expected above it, t2 leaving k a margin of four
+//     standard deviations); pass 1 over the other blocks with the refined
+//     threshold, where hits are rare enough that most tiles need only one
+//     ballot;
+//  3. select: the k largest keys of each buffer in descending order (a
+//     buffer of at most 2k keys sorted whole in LDS, a larger one first cut
+//     to its k best by a radix select); a query whose buffer overflowed,
+//     whose sampled threshold kept fewer than min(k, window) candidates, or
+//     whose k-th kept key scores below the refined threshold (so that a
+//     better candidate of pass 1 could have been missed) is flagged for the
+//     exhaustive fallback and gets no shortlist;
+//  4. rescore: one wave per query, 16 lanes per shortlist entry, computes the
+//     exact Hamming distances; the wave minimum of (distance << 32 | library
+//     index) is merged into the query's key;
 //  5. fallback: the flagged queries are listed on the device and their whole
 //     windows scanned, one wave per 512-row unit, into the same keys.
 #include <algorithm>
