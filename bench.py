@@ -17,7 +17,9 @@ The default run also measures, under extra keys of the same line, the batched
 form ("batched": 2M + 2M library, 200,000 queries of mixed narrow and open
 windows in one persistent hipGraph launch) and the learned form at a moderate
 size ("learned": the large workload's library and queries, a D-1024-256 MLP
-trained on the GPU on 300,000 labelled training queries, k = 64 shortlists).
+trained on the GPU on 300,000 labelled training queries, k = 64 shortlists)
+and the cascade ("cascade": the same library and queries, +-20 ppm standard
+search, 1% FDR, +-500 Da open search of the unidentified queries, 1% FDR).
 
 Prints one JSON line: comparisons/s (sum of candidate-window sizes per
 second), queries/s, the roofline of each kernel measured with HIP events
@@ -199,7 +201,7 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the CPU baselines and the extra legs (for profiler runs)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="large workload only: skip the batched and learned legs")
+                    help="large workload only: skip the learned, cascade and batched legs")
     ap.add_argument("--engine", default="mfma_fp4", choices=list(ENGINE_SOURCES),
                     help="search engine of the timed step (all are bit-exact)")
     ap.add_argument("--skip-mfma", action="store_true",
@@ -446,6 +448,11 @@ def bench_large(args, w, dev, jobs):
                                              args.k)
         line["learned"] = learned
         del tr
+    cascade_result = None
+    if extra:
+        # the cascade (narrow search, FDR, open search of the rest) on the same
+        # library and queries
+        line["cascade"], cascade_result = cascade_leg(args, w, g, ctx, dev, q_dev, q_pmz, q_ch)
     ctx.close()
     del q_dev, l_pmz, l_ch, q_pmz, q_ch, q_hv, out_idx, out_dist
     torch.cuda.empty_cache()
@@ -474,6 +481,8 @@ def bench_large(args, w, dev, jobs):
         if learned_state is not None:
             finish_learned(line["learned"], learned_state, sample, s, o_idx, o_dist, o_qhv, t,
                            desc)
+        if cascade_result is not None:
+            line["cascade"]["cpu_baseline"] = cascade_cpu_baseline(s, sample, g, *cascade_result)
     if finish_batched is not None:
         finish_batched()
     return line
@@ -951,7 +960,6 @@ def bench_cascade(args, w, dev, jobs):
     t0 = time.time()
     g = make_workload(w, n_ref=args.n_ref, n_query=args.n_query)
     lib, q = g.library, g.queries
-    n_ref = g.meta["n_ref"]
     log(f"generated {lib.n} library + {q.n} query spectra in {time.time() - t0:.1f}s")
     want_cpu = args.cpu_sample > 0 and not args.profile_only
     sample = random_sample(q.n, args.cpu_sample) if want_cpu else None
@@ -968,6 +976,25 @@ def bench_cascade(args, w, dev, jobs):
     q_dev = h.to_device_csr(*q_csr, dev)
     q_pmz = torch.from_numpy(q.pmz).to(dev)
     q_ch = torch.from_numpy(q.charge).to(dev)
+    line, result = cascade_leg(args, w, g, ctx, dev, q_dev, q_pmz, q_ch)
+    ctx.close()
+    jobs.close()
+    if side is not None:
+        line["cpu_baseline"] = cascade_cpu_baseline(side.result(), sample, g, *result)
+    return line
+
+
+def cascade_leg(args, w, g, ctx, dev, q_dev, q_pmz, q_ch):
+    """Timed cascade steps on an encoded context: each step encodes the
+    queries and runs homs_cascade_search on the fp4 engine. Returns the line
+    (cpu_baseline None) and what cascade_cpu_baseline needs besides the
+    oracle side: (n_ref, top-1 indices, distances, stages)."""
+    import torch
+
+    import paper_2211_16422_amd.hyperoms as h
+
+    lib, q = g.library, g.queries
+    n_ref = g.meta["n_ref"]
     decoy = torch.from_numpy((np.arange(lib.n) >= n_ref).astype(np.uint8)).to(dev)
     q_hv = torch.empty((q.n, ctx.words), dtype=torch.int32, device=dev)
     narrow, wide, level = (h.TOL_PPM, 20.0), (h.TOL_DA, 500.0), 0.01
@@ -1000,9 +1027,8 @@ def bench_cascade(args, w, dev, jobs):
     pairs = pairs_narrow + pairs_open
     search_ms = prof["search_ms"] / max(args.steps, 1)  # both stages' search kernels
     tflops = 2.0 * w.dim * pairs / (search_ms * 1e-3) / 1e12
-    log(f"stage 1: {n1}, stage 2: {n2}, unidentified {q.n - n1 - n2}; pairs narrow "
+    log(f"cascade: stage 1: {n1}, stage 2: {n2}, unidentified {q.n - n1 - n2}; pairs narrow "
         f"{pairs_narrow:.3e}, open {pairs_open:.3e}; search kernels {search_ms:.1f} ms per step")
-    ctx.close()
     line = {
         "metric": "cascade search queries/s (+-20 ppm standard search, 1% FDR, +-500 Da open "
                   f"search of the unidentified queries, 1% FDR), D={w.dim}",
@@ -1024,11 +1050,7 @@ def bench_cascade(args, w, dev, jobs):
                      "kernel_ms": round(search_ms, 3), "ops_per_pair": 2 * w.dim},
         "cpu_baseline": None,
     }
-    jobs.close()
-    if side is not None:
-        line["cpu_baseline"] = cascade_cpu_baseline(side.result(), sample, g, n_ref, idx, dist,
-                                                    stage)
-    return line
+    return line, (n_ref, idx, dist, stage)
 
 
 def cascade_cpu_baseline(side, sample, g, n_ref, gpu_idx, gpu_dist, gpu_stage):
