@@ -7,8 +7,8 @@
 // Workgroup tile 128 x 128 with four waves in a 2 x 2 grid (64 x 64 per
 // wave, 2 x 2 MFMA tiles of 32 x 32). K advances 32 at a time through a
 // double-buffered LDS stage (rows padded to 80 bytes so 16 lanes of a
-// 16-byte read hit 64 distinct banks); the next stage's global loads are in
-// flight while the current stage's MFMAs run.
+// 16-byte read hit 64 distinct banks); the global loads of the next two
+// stages are in flight while the current stage's MFMAs run.
 //
 // Operand layout of 32x32x16 bf16 (checked on gfx950): lane l supplies row
 // (l % 32) and the 8 consecutive k of group (l / 32); accumulator register r
@@ -92,12 +92,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
 
     const int nk = K / kTK;
-    st = load_stage(a_row, b_row, 0);
-    store_stage(st, sa_dst, sb_dst, 0);
-    __syncthreads();
-    for (int s = 0; s < nk; ++s) {
-        const int buf = s & 1;
-        if (s + 1 < nk) st = load_stage(a_row, b_row, (s + 1) * kTK);
+    // Two K steps of loads in flight, in two named register sets (a copy
+    // from one set to the other would wait for the newer loads): at step s
+    // the set of step s + 1 is stored to LDS while the loads of step s + 2
+    // fill the other set, so each load has two steps of matrix work to land.
+    // The loads are unconditional (past the last step they re-read it), so
+    // that the compiler's wait before a store counts only the older set.
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             bf16x8 av[2], bv[2];
@@ -115,7 +116,23 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0,
                                                                        0, 0);
         }
-        if (s + 1 < nk) store_stage(st, sa_dst, sb_dst, buf ^ 1);
+    };
+    Stage st1;
+    st = load_stage(a_row, b_row, 0);
+    store_stage(st, sa_dst, sb_dst, 0);
+    if (nk > 1) st1 = load_stage(a_row, b_row, kTK);
+    __syncthreads();
+    for (int s = 0; s < nk; s += 2) {
+        // LDS buffer 0 holds step s, st1 step s + 1
+        st = load_stage(a_row, b_row, min(s + 2, nk - 1) * kTK);
+        compute(0);
+        if (s + 1 < nk) store_stage(st1, sa_dst, sb_dst, 1);
+        __syncthreads();
+        if (s + 1 >= nk) break;
+        // LDS buffer 1 holds step s + 1, st step s + 2
+        st1 = load_stage(a_row, b_row, min(s + 3, nk - 1) * kTK);
+        compute(1);
+        if (s + 2 < nk) store_stage(st, sa_dst, sb_dst, 0);
         __syncthreads();
     }
 
