@@ -672,7 +672,7 @@ def learned_leg(args, w, ctx, dev, q_hv, q_pmz, q_ch, train, desc, k):
 
 def finish_learned(line, state, sample, side, o_idx, o_dist, o_qhv, t, desc):
     """The learned leg's oracle baseline and parity sample: the oracle's
-    exhaustive search (the judge of top-1 agreement) on the sampled queries;
+    exhaustive search (the reference answer for top-1 agreement) on the sampled queries;
     the learned answers must agree with it at the rate measured on the GPU,
     and every returned distance must be the exact Hamming distance of the
     returned reference, computed from the oracle's own rows."""
@@ -687,7 +687,7 @@ def finish_learned(line, state, sample, side, o_idx, o_dist, o_qhv, t, desc):
         ham = np.bitwise_count(rows ^ o_qhv[ok]).sum(axis=1)
         exact = bool(found.all() and np.array_equal(ham, dist[ok]))
     line["cpu_baseline"] = cpu_entry(len(sample) / t, "queries/s",
-                                     "oracle exhaustive top-1 (the judge) of " + desc, t)
+                                     "oracle exhaustive top-1 (the reference answer) of " + desc, t)
     line["parity_sample"] = {"queries": int(len(sample)), "sampling": f"random, seed {SAMPLE_SEED}",
                              "top1_agreement_vs_oracle": agree,
                              "fallback_in_sample": int((fb != 0).sum()),
